@@ -1,0 +1,225 @@
+"""Plain CPU oracle for the compressible-Euler building blocks of FDBB.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  The product library
+never loads it and shares no code with it.
+
+The arithmetic lives in ``fdbb_oracle.c`` (plain single-threaded C, FP64,
+compiled with ``-O2 -ffp-contract=off``).  This module only builds that file
+with gcc and marshals numpy arrays into it; it holds none of the method's
+arithmetic.  Every function takes and returns SoA arrays of shape
+``(fields, n)`` (C-contiguous float64), matching the C layout with ld = n.
+
+Sections cited below are those of the FDBB paper:
+  * cons2prim / prim2cons       -- Sec. 2.2, "Variables" (conversion figure)
+  * eos                         -- Sec. 2.2, "Equations of state" (p_rhoe)
+  * flux                        -- Sec. 2.2, "Inviscid Fluxes" (flux tensor)
+  * flux_jacobian               -- Fig. 1 / Sec. 2.2 (derivative of the above)
+  * riemann_invariants, cons2char, char2cons -- Fig. 1 (named building blocks)
+  * flux_adjoint                -- transpose of the flux Jacobians
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCE = os.path.join(_HERE, "fdbb_oracle.c")
+LIBRARY = os.path.join(_HERE, "liboracle_fdbb.so")
+
+_i64 = ctypes.c_int64
+_dp = ctypes.c_void_p
+_int = ctypes.c_int
+_dbl = ctypes.c_double
+
+CFLAGS = ["-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
+def compile_source(src: str, out: str) -> str:
+    """Compile one oracle source file into a shared library with gcc."""
+    tmp = out + ".tmp"
+    subprocess.run(["gcc", *CFLAGS, "-o", tmp, src, "-lm"], check=True)
+    os.replace(tmp, out)
+    return out
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(LIBRARY):
+        compile_source(SOURCE, LIBRARY)
+    return LIBRARY
+
+
+def _soa(a: np.ndarray, fields: int) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.ndim != 2 or a.shape[0] != fields:
+        raise ValueError(f"expected an array of shape ({fields}, n), got {a.shape}")
+    return a
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise ValueError("oracle rejected dim or direction")
+
+
+class Oracle:
+    """numpy front end over one compiled copy of ``fdbb_oracle.c``."""
+
+    def __init__(self, path: str):
+        lib = ctypes.CDLL(path)
+        sig = [_int, _dbl, _dp, _i64, _dp, _i64, _i64]
+        for name in ("oracle_cons2prim", "oracle_prim2cons", "oracle_flux",
+                     "oracle_flux_jacobian", "oracle_riemann_invariants"):
+            getattr(lib, name).argtypes = sig
+            getattr(lib, name).restype = _int
+        lib.oracle_eos.argtypes = [_int, _dbl, _dp, _i64, _dp, _dp, _i64]
+        lib.oracle_eos.restype = _int
+        for name in ("oracle_cons2char", "oracle_char2cons"):
+            getattr(lib, name).argtypes = [_int, _int, _dbl, _dp, _i64, _dp, _i64, _i64]
+            getattr(lib, name).restype = _int
+        lib.oracle_flux_adjoint.argtypes = [_int, _int, _dbl, _dp, _i64, _dp, _i64,
+                                            _dp, _i64, _i64]
+        lib.oracle_flux_adjoint.restype = _int
+        self.lib = lib
+        self.path = path
+
+    def cons2prim(self, dim, gamma, U):
+        U = _soa(U, dim + 2)
+        n = U.shape[1]
+        V = np.empty_like(U)
+        _check(self.lib.oracle_cons2prim(dim, gamma, _ptr(U), n, _ptr(V), n, n))
+        return V
+
+    def prim2cons(self, dim, gamma, V):
+        V = _soa(V, dim + 2)
+        n = V.shape[1]
+        U = np.empty_like(V)
+        _check(self.lib.oracle_prim2cons(dim, gamma, _ptr(V), n, _ptr(U), n, n))
+        return U
+
+    def eos(self, dim, gamma, U):
+        """Returns (p, c), each of shape (n,)."""
+        U = _soa(U, dim + 2)
+        n = U.shape[1]
+        p = np.empty(n)
+        c = np.empty(n)
+        _check(self.lib.oracle_eos(dim, gamma, _ptr(U), n, _ptr(p), _ptr(c), n))
+        return p, c
+
+    def flux(self, dim, gamma, U):
+        """Returns F with shape (K*D, n); field r*D + d is row r of F_d."""
+        U = _soa(U, dim + 2)
+        n = U.shape[1]
+        F = np.empty(((dim + 2) * dim, n))
+        _check(self.lib.oracle_flux(dim, gamma, _ptr(U), n, _ptr(F), n, n))
+        return F
+
+    def flux_jacobian(self, dim, gamma, U):
+        """Returns A with shape (D, n, K, K): A[d, i] is the Jacobian block of
+        point i in direction d (point-major, row-major blocks)."""
+        U = _soa(U, dim + 2)
+        n = U.shape[1]
+        K = dim + 2
+        A = np.empty((dim, n, K, K))
+        _check(self.lib.oracle_flux_jacobian(dim, gamma, _ptr(U), n, _ptr(A), n, n))
+        return A
+
+    def riemann_invariants(self, dim, gamma, U):
+        """Returns R with shape (2*D+1, n): (w-_0, w+_0, ..., s)."""
+        U = _soa(U, dim + 2)
+        n = U.shape[1]
+        R = np.empty((2 * dim + 1, n))
+        _check(self.lib.oracle_riemann_invariants(dim, gamma, _ptr(U), n, _ptr(R), n, n))
+        return R
+
+    def cons2char(self, dim, direction, gamma, U):
+        U = _soa(U, dim + 2)
+        n = U.shape[1]
+        W = np.empty_like(U)
+        _check(self.lib.oracle_cons2char(dim, direction, gamma, _ptr(U), n, _ptr(W), n, n))
+        return W
+
+    def char2cons(self, dim, direction, gamma, W):
+        W = _soa(W, dim + 2)
+        n = W.shape[1]
+        U = np.empty_like(W)
+        _check(self.lib.oracle_char2cons(dim, direction, gamma, _ptr(W), n, _ptr(U), n, n))
+        return U
+
+    def flux_adjoint(self, dim, direction, gamma, U, Fbar):
+        """Ubar = sum_d A_d^T Fbar_d (direction == -1, Fbar of shape (K*D, n))
+        or A_dir^T Fbar (direction >= 0, Fbar of shape (K, n))."""
+        K = dim + 2
+        U = _soa(U, K)
+        n = U.shape[1]
+        Fbar = _soa(Fbar, K * dim if direction < 0 else K)
+        if Fbar.shape[1] != n:
+            raise ValueError("Fbar and U differ in length")
+        Ub = np.empty_like(U)
+        _check(self.lib.oracle_flux_adjoint(dim, direction, gamma, _ptr(U), n,
+                                            _ptr(Fbar), n, _ptr(Ub), n, n))
+        return Ub
+
+    def fused(self, dim, gamma, U):
+        """The fused pass is, by definition, the flux, the flux Jacobians and
+        the Riemann invariants of the same state."""
+        return (self.flux(dim, gamma, U), self.flux_jacobian(dim, gamma, U),
+                self.riemann_invariants(dim, gamma, U))
+
+
+_default = None
+
+
+def default() -> Oracle:
+    global _default
+    if _default is None:
+        if not os.path.exists(LIBRARY):
+            build(force=True)
+        _default = Oracle(LIBRARY)
+    return _default
+
+
+def cons2prim(dim, gamma, U):
+    return default().cons2prim(dim, gamma, U)
+
+
+def prim2cons(dim, gamma, V):
+    return default().prim2cons(dim, gamma, V)
+
+
+def eos(dim, gamma, U):
+    return default().eos(dim, gamma, U)
+
+
+def flux(dim, gamma, U):
+    return default().flux(dim, gamma, U)
+
+
+def flux_jacobian(dim, gamma, U):
+    return default().flux_jacobian(dim, gamma, U)
+
+
+def riemann_invariants(dim, gamma, U):
+    return default().riemann_invariants(dim, gamma, U)
+
+
+def cons2char(dim, direction, gamma, U):
+    return default().cons2char(dim, direction, gamma, U)
+
+
+def char2cons(dim, direction, gamma, W):
+    return default().char2cons(dim, direction, gamma, W)
+
+
+def flux_adjoint(dim, direction, gamma, U, Fbar):
+    return default().flux_adjoint(dim, direction, gamma, U, Fbar)
+
+
+def fused(dim, gamma, U):
+    return default().fused(dim, gamma, U)

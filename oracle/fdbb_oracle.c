@@ -1,0 +1,355 @@
+/*
+ * Plain CPU oracle for the compressible-Euler building blocks of
+ * "FDBB: Fluid Dynamics Building Blocks" (Moeller, Jaeschke).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
+ * load this file; only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg use it.  It shares no code with the HIP library.
+ *
+ * Every function is a direct, single-threaded FP64 evaluation of the
+ * per-point definition, one point at a time, with no blocking or fusion.
+ * Build with -O2 -ffp-contract=off so that no multiply-add is contracted.
+ *
+ * Notation (Sec. 2.2, paragraph "Variables"): the conservative state in
+ * D dimensions is U = (rho, m_1..m_D, E) with m = rho*v the momentum and E
+ * the total energy per unit volume (the paper's "rho E").  K = D + 2.
+ * Perfect gas with adiabatic index gamma = c_p/c_v (paper: 7/2 over 5/2).
+ *
+ * Array layout, shared by every function:
+ *   a field set is one base pointer plus a leading dimension ld (elements);
+ *   component k of point i lives at base[k*ld + i]                   (SoA);
+ *   the flux tensor F is N_U x N_D row-major (Sec. 2.1, "Block Expressions",
+ *   row-major default; Sec. 2.2, "Inviscid Fluxes", 5x3 block), so flux
+ *   component (r, d) is field r*D + d;
+ *   flux Jacobian blocks are stored point-major: entry (r, c) of
+ *   A_d at point i is A[(d*ldA + i)*K*K + r*K + c].
+ *
+ * Return value: 0 on success, -1 for an unsupported dim or direction.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#define ORACLE_MAXK 5
+
+static int dim_ok(int dim) { return dim >= 1 && dim <= 3; }
+
+/* Primitive quantities of one conservative state (Sec. 2.2, "Variables";
+ * pressure of the perfect gas, p = (gamma-1) * rho * e, with e the specific
+ * internal energy, as in the p_rhoe member of the EOS prototype). */
+typedef struct {
+    double rho;
+    double v[3];
+    double q;   /* |v|^2 */
+    double E;
+    double p;
+} point_state;
+
+static point_state load_cons(int dim, double gamma, const double *U,
+                             int64_t ld, int64_t i)
+{
+    point_state s;
+    int k;
+    double kinetic, e;
+    s.rho = U[0 * ld + i];
+    s.q = 0.0;
+    for (k = 0; k < 3; ++k)
+        s.v[k] = 0.0;
+    for (k = 0; k < dim; ++k) {
+        s.v[k] = U[(1 + k) * ld + i] / s.rho;
+        s.q = s.q + s.v[k] * s.v[k];
+    }
+    s.E = U[(dim + 1) * ld + i];
+    /* specific internal energy e = E/rho - |v|^2/2, then p = (gamma-1) rho e */
+    kinetic = 0.5 * s.q;
+    e = s.E / s.rho - kinetic;
+    s.p = (gamma - 1.0) * s.rho * e;
+    return s;
+}
+
+/* Conservative -> primitive, V = (rho, v_1..v_D, p)
+ * (Sec. 2.2, "Variables", the conversion figure). */
+int oracle_cons2prim(int dim, double gamma, const double *U, int64_t ldU,
+                     double *V, int64_t ldV, int64_t n)
+{
+    int64_t i;
+    int k;
+    if (!dim_ok(dim))
+        return -1;
+    for (i = 0; i < n; ++i) {
+        point_state s = load_cons(dim, gamma, U, ldU, i);
+        V[0 * ldV + i] = s.rho;
+        for (k = 0; k < dim; ++k)
+            V[(1 + k) * ldV + i] = s.v[k];
+        V[(dim + 1) * ldV + i] = s.p;
+    }
+    return 0;
+}
+
+/* Primitive -> conservative: m = rho v, E = rho e + rho |v|^2 / 2 with
+ * rho e = p / (gamma - 1) (Sec. 2.2, "Variables"). */
+int oracle_prim2cons(int dim, double gamma, const double *V, int64_t ldV,
+                     double *U, int64_t ldU, int64_t n)
+{
+    int64_t i;
+    int k;
+    if (!dim_ok(dim))
+        return -1;
+    for (i = 0; i < n; ++i) {
+        double rho = V[0 * ldV + i];
+        double p = V[(dim + 1) * ldV + i];
+        double q = 0.0;
+        double v[3];
+        for (k = 0; k < dim; ++k) {
+            v[k] = V[(1 + k) * ldV + i];
+            q = q + v[k] * v[k];
+        }
+        U[0 * ldU + i] = rho;
+        for (k = 0; k < dim; ++k)
+            U[(1 + k) * ldU + i] = rho * v[k];
+        U[(dim + 1) * ldU + i] = p / (gamma - 1.0) + 0.5 * rho * q;
+    }
+    return 0;
+}
+
+/* Equation of state of the perfect gas (Sec. 2.2, "Equations of state"):
+ * pressure p and speed of sound c = sqrt(gamma p / rho).  Either output
+ * may be NULL. */
+int oracle_eos(int dim, double gamma, const double *U, int64_t ldU,
+               double *p, double *c, int64_t n)
+{
+    int64_t i;
+    if (!dim_ok(dim))
+        return -1;
+    for (i = 0; i < n; ++i) {
+        point_state s = load_cons(dim, gamma, U, ldU, i);
+        if (p)
+            p[i] = s.p;
+        if (c)
+            c[i] = sqrt(gamma * s.p / s.rho);
+    }
+    return 0;
+}
+
+/* Inviscid flux tensor (Sec. 2.2, "Inviscid Fluxes"):
+ *   F(U) = [ rho v ; rho v (x) v + I p ; v (rho E + p) ],
+ * an N_U x N_D block; column d is the flux F_d in direction d. */
+int oracle_flux(int dim, double gamma, const double *U, int64_t ldU,
+                double *F, int64_t ldF, int64_t n)
+{
+    int64_t i;
+    int d, r;
+    if (!dim_ok(dim))
+        return -1;
+    for (i = 0; i < n; ++i) {
+        point_state s = load_cons(dim, gamma, U, ldU, i);
+        for (d = 0; d < dim; ++d) {
+            double col[ORACLE_MAXK];
+            col[0] = s.rho * s.v[d];
+            for (r = 0; r < dim; ++r)
+                col[1 + r] = s.rho * s.v[r] * s.v[d] + (r == d ? s.p : 0.0);
+            col[dim + 1] = s.v[d] * (s.E + s.p);
+            for (r = 0; r < dim + 2; ++r)
+                F[(r * dim + d) * ldF + i] = col[r];
+        }
+    }
+    return 0;
+}
+
+/* Flux Jacobian A_d = dF_d/dU of one point, written out term by term from
+ * the flux tensor and p = (gamma-1)(E - rho |v|^2 / 2).  The paper names
+ * the flux Jacobians (Fig. 1) but leaves them unfinished (Sec. 2.2,
+ * "Inviscid Fluxes"); this is the exact derivative.  With
+ * phi = (gamma-1)|v|^2/2 and H = (E + p)/rho:
+ *   dp/drho = phi, dp/dm_j = -(gamma-1) v_j, dp/dE = gamma-1. */
+static void jacobian_point(int dim, double gamma, const point_state *s, int d,
+                           double A[ORACLE_MAXK][ORACLE_MAXK])
+{
+    int K = dim + 2, r, c, i, j;
+    double g1 = gamma - 1.0;
+    double phi = 0.5 * g1 * s->q;
+    double H = (s->E + s->p) / s->rho;
+    double dp_drho = phi;
+    double dp_dm[3];
+    double dp_dE = g1;
+
+    for (j = 0; j < dim; ++j)
+        dp_dm[j] = -g1 * s->v[j];
+    for (r = 0; r < K; ++r)
+        for (c = 0; c < K; ++c)
+            A[r][c] = 0.0;
+
+    /* row 0: F_d[0] = m_d */
+    A[0][1 + d] = 1.0;
+
+    /* rows 1..D: F_d[1+i] = m_i m_d / rho + delta_id p */
+    for (i = 0; i < dim; ++i) {
+        A[1 + i][0] = -s->v[i] * s->v[d] + (i == d ? dp_drho : 0.0);
+        for (j = 0; j < dim; ++j) {
+            double t = 0.0;
+            if (i == j)
+                t = t + s->v[d];
+            if (j == d)
+                t = t + s->v[i];
+            if (i == d)
+                t = t + dp_dm[j];
+            A[1 + i][1 + j] = t;
+        }
+        A[1 + i][K - 1] = (i == d ? dp_dE : 0.0);
+    }
+
+    /* row K-1: F_d[K-1] = m_d (E + p) / rho */
+    A[K - 1][0] = s->v[d] * dp_drho - s->v[d] * H;
+    for (j = 0; j < dim; ++j)
+        A[K - 1][1 + j] = (j == d ? H : 0.0) + s->v[d] * dp_dm[j];
+    A[K - 1][K - 1] = s->v[d] * (1.0 + dp_dE);
+}
+
+/* Flux Jacobians A_d for every direction d (Fig. 1, "flux-Jacobians"). */
+int oracle_flux_jacobian(int dim, double gamma, const double *U, int64_t ldU,
+                         double *A, int64_t ldA, int64_t n)
+{
+    int64_t i;
+    int d, r, c, K = dim + 2;
+    double blk[ORACLE_MAXK][ORACLE_MAXK];
+    if (!dim_ok(dim))
+        return -1;
+    for (i = 0; i < n; ++i) {
+        point_state s = load_cons(dim, gamma, U, ldU, i);
+        for (d = 0; d < dim; ++d) {
+            double *dst = A + (d * ldA + i) * (int64_t)(K * K);
+            jacobian_point(dim, gamma, &s, d, blk);
+            for (r = 0; r < K; ++r)
+                for (c = 0; c < K; ++c)
+                    dst[r * K + c] = blk[r][c];
+        }
+    }
+    return 0;
+}
+
+/* Riemann invariants (Fig. 1, "Riemann invariants"): for each direction d
+ * the pair w-_d = v_d - 2c/(gamma-1), w+_d = v_d + 2c/(gamma-1), followed
+ * by the entropy s = p / rho^gamma.  Output fields, in order:
+ * (w-_0, w+_0, ..., w-_{D-1}, w+_{D-1}, s). */
+int oracle_riemann_invariants(int dim, double gamma, const double *U,
+                              int64_t ldU, double *R, int64_t ldR, int64_t n)
+{
+    int64_t i;
+    int d;
+    if (!dim_ok(dim))
+        return -1;
+    for (i = 0; i < n; ++i) {
+        point_state s = load_cons(dim, gamma, U, ldU, i);
+        double c = sqrt(gamma * s.p / s.rho);
+        double two_c_over_g1 = 2.0 * c / (gamma - 1.0);
+        for (d = 0; d < dim; ++d) {
+            R[(2 * d + 0) * ldR + i] = s.v[d] - two_c_over_g1;
+            R[(2 * d + 1) * ldR + i] = s.v[d] + two_c_over_g1;
+        }
+        R[(2 * dim) * ldR + i] = s.p / pow(s.rho, gamma);
+    }
+    return 0;
+}
+
+/* Characteristic variables for direction dir (Fig. 1, "characteristic
+ * variables"), taken pointwise as W = (w-_dir, s, v_j for j != dir in
+ * ascending j, w+_dir): the invariants ordered by the eigenvalues
+ * v_dir - c, v_dir (D times), v_dir + c of A_dir. */
+int oracle_cons2char(int dim, int dir, double gamma, const double *U,
+                     int64_t ldU, double *W, int64_t ldW, int64_t n)
+{
+    int64_t i;
+    int j, slot;
+    if (!dim_ok(dim) || dir < 0 || dir >= dim)
+        return -1;
+    for (i = 0; i < n; ++i) {
+        point_state s = load_cons(dim, gamma, U, ldU, i);
+        double c = sqrt(gamma * s.p / s.rho);
+        double two_c_over_g1 = 2.0 * c / (gamma - 1.0);
+        W[0 * ldW + i] = s.v[dir] - two_c_over_g1;
+        W[1 * ldW + i] = s.p / pow(s.rho, gamma);
+        slot = 2;
+        for (j = 0; j < dim; ++j) {
+            if (j == dir)
+                continue;
+            W[slot * ldW + i] = s.v[j];
+            slot = slot + 1;
+        }
+        W[(dim + 1) * ldW + i] = s.v[dir] + two_c_over_g1;
+    }
+    return 0;
+}
+
+/* Inverse of oracle_cons2char: from w-, w+ recover v_dir and c, from c and
+ * s = p/rho^gamma recover rho = (c^2 / (gamma s))^(1/(gamma-1)) and
+ * p = rho c^2 / gamma, then build U from (rho, v, p). */
+int oracle_char2cons(int dim, int dir, double gamma, const double *W,
+                     int64_t ldW, double *U, int64_t ldU, int64_t n)
+{
+    int64_t i;
+    int j, slot;
+    double g1 = gamma - 1.0;
+    if (!dim_ok(dim) || dir < 0 || dir >= dim)
+        return -1;
+    for (i = 0; i < n; ++i) {
+        double wm = W[0 * ldW + i];
+        double s = W[1 * ldW + i];
+        double wp = W[(dim + 1) * ldW + i];
+        double v[3];
+        double c, rho, p, q;
+        slot = 2;
+        for (j = 0; j < dim; ++j) {
+            if (j == dir)
+                continue;
+            v[j] = W[slot * ldW + i];
+            slot = slot + 1;
+        }
+        v[dir] = 0.5 * (wp + wm);
+        c = 0.25 * g1 * (wp - wm);
+        rho = pow(c * c / (gamma * s), 1.0 / g1);
+        p = rho * c * c / gamma;
+        q = 0.0;
+        for (j = 0; j < dim; ++j)
+            q = q + v[j] * v[j];
+        U[0 * ldU + i] = rho;
+        for (j = 0; j < dim; ++j)
+            U[(1 + j) * ldU + i] = rho * v[j];
+        U[(dim + 1) * ldU + i] = p / g1 + 0.5 * rho * q;
+    }
+    return 0;
+}
+
+/* Adjoint of the flux map: Ubar = sum_d A_d(U)^T Fbar_d, with A_d built as
+ * an explicit K x K matrix and multiplied in transposed form.
+ * dir == -1: Fbar has the flux tensor's layout (field r*D + d), summed
+ * over all d.  dir in [0, D): Fbar holds K fields, Fbar_dir only. */
+int oracle_flux_adjoint(int dim, int dir, double gamma, const double *U,
+                        int64_t ldU, const double *Fb, int64_t ldFb,
+                        double *Ub, int64_t ldUb, int64_t n)
+{
+    int64_t i;
+    int d, r, c, K = dim + 2;
+    double blk[ORACLE_MAXK][ORACLE_MAXK];
+    if (!dim_ok(dim) || dir < -1 || dir >= dim)
+        return -1;
+    for (i = 0; i < n; ++i) {
+        point_state s = load_cons(dim, gamma, U, ldU, i);
+        double acc[ORACLE_MAXK];
+        for (c = 0; c < K; ++c)
+            acc[c] = 0.0;
+        for (d = 0; d < dim; ++d) {
+            if (dir >= 0 && d != dir)
+                continue;
+            jacobian_point(dim, gamma, &s, d, blk);
+            for (c = 0; c < K; ++c) {
+                for (r = 0; r < K; ++r) {
+                    int64_t field = (dir >= 0) ? r : (r * dim + d);
+                    acc[c] = acc[c] + blk[r][c] * Fb[field * ldFb + i];
+                }
+            }
+        }
+        for (c = 0; c < K; ++c)
+            Ub[c * ldUb + i] = acc[c];
+    }
+    return 0;
+}
