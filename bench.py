@@ -1,0 +1,318 @@
+"""Throughput of the fused 3D Euler pass (flux tensor + three 5x5 flux
+Jacobians + Riemann invariants) on one MI355X, against the HBM roofline.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--extras]
+
+One step is one fused pass over N = 2^24 points of a seeded synthetic 3D
+state (rho, p ~ U[0.5, 2], v_i ~ N(0, 0.5^2)), FP64 storage, inputs and
+outputs resident in HBM.  Prints one JSON line.  ``--extras`` adds the other
+building blocks (FP32 storage, single-op launches, 1D ops, adjoint).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import threading
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+METRIC = "3D Euler flux+Jacobian Gpoints/s, % HBM roofline; served p50/p99 latency"
+GAMMA = 1.4
+
+# Algorithmic bytes per point (each input read once, each output written once).
+def fused_bytes(dim: int, es: int) -> int:
+    K = dim + 2
+    return es * (K + K * dim + dim * K * K + 2 * dim + 1)
+
+
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "fused3d_f64_2p24_traffic.json")
+KERNEL_SOURCES = ["euler_point.hpp", "euler_tiles.hpp", "kernels_fused.hip"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1809_09851_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(n: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    try:
+        with open(PROFILE_TRAFFIC) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_hash") != kernel_hash() or rec.get("n") != n:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def timed_launches(fn, steps: int, warmup: int):
+    """Run fn() warmup + steps times; returns (wall ms per step, mean HIP-event
+    ms per launch), events recorded on the stream the kernels run on."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    stream = torch.cuda.current_stream()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        starts[k].record(stream)
+        fn()
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    ev = sum(s.elapsed_time(e) for s, e in zip(starts, ends)) / steps
+    return wall, ev
+
+
+def device_state(dim: int, n: int, seed: int, dtype):
+    """Seeded primitive state -> GPU -> conservative state via the library."""
+    import torch
+    from paper_1809_09851_amd import fdbb as F
+    from paper_1809_09851_amd import inputs
+    V = inputs.gaussian(dim, n, seed) if dim > 1 else inputs.uniform_1d(n, seed)
+    Vg = F.to_fields(torch.from_numpy(V).to(dtype).cuda())
+    Ug = F.empty_fields(dim + 2, n, dtype)
+    F.fdbb_prim2cons(dim, GAMMA, Vg, Ug)
+    torch.cuda.synchronize()
+    del Vg
+    return Ug
+
+
+def cpu_baseline(n_sample: int = 1 << 24, seed: int = 1):
+    """The oracle's fused pass (flux, Jacobians, invariants) on the first
+    n_sample points of the same workload, split over host threads, each
+    calling the unchanged single-threaded oracle on its own range."""
+    import numpy as np
+    import oracle
+    from paper_1809_09851_amd import inputs
+    V = inputs.gaussian(3, n_sample, seed)
+    U = oracle.prim2cons(3, GAMMA, V)
+    threads = max(1, min(16, os.cpu_count() or 1))
+    chunk = 1 << 14
+    ranges = [(s, min(s + chunk, n_sample)) for s in range(0, n_sample, chunk)]
+    lock = threading.Lock()
+    todo = list(ranges)
+
+    def worker():
+        while True:
+            with lock:
+                if not todo:
+                    return
+                a, b = todo.pop()
+            Us = np.ascontiguousarray(U[:, a:b])
+            oracle.flux(3, GAMMA, Us)
+            oracle.flux_jacobian(3, GAMMA, Us)
+            oracle.riemann_invariants(3, GAMMA, Us)
+
+    t0 = time.perf_counter()
+    ts = [threading.Thread(target=worker) for _ in range(threads)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    wall = time.perf_counter() - t0
+    return {"value": round(n_sample / wall / 1e9, 6), "unit": "Gpoints/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {n_sample} points of the 3D N=2^24 workload (seed 1), fused "
+                      f"flux+Jacobians+invariants, {threads} threads on disjoint 2^14-point ranges, "
+                      f"{wall:.2f} s wall"}
+
+
+def bench_fused(n: int, steps: int, warmup: int, dtype, label: str):
+    import torch
+    from paper_1809_09851_amd import fdbb as F
+    dim = 3
+    U = device_state(dim, n, 1, dtype)
+    Fg = F.empty_fields(15, n, dtype)
+    A = F.empty_blocks(dim, n, dtype)
+    R = F.empty_fields(7, n, dtype)
+
+    def step():
+        F.fdbb_euler_fused(dim, GAMMA, U, Fg, A, R)
+
+    wall, ev = timed_launches(step, steps, warmup)
+    es = 8 if dtype == torch.float64 else 4
+    nbytes = fused_bytes(dim, es) * n
+    out = {"label": label, "n": n, "wall_ms": wall, "kernel_ms": ev,
+           "gpoints_s": n / (wall * 1e-3) / 1e9, "kernel_gpoints_s": n / (ev * 1e-3) / 1e9,
+           "algorithmic_bytes": nbytes, "achieved_gbs": nbytes / (ev * 1e-3) / 1e9}
+    del U, Fg, A, R
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_separate(n: int, steps: int, warmup: int, dtype):
+    """The plain form: flux, Jacobian and invariants as three launches."""
+    import torch
+    from paper_1809_09851_amd import fdbb as F
+    dim = 3
+    U = device_state(dim, n, 1, dtype)
+    Fg = F.empty_fields(15, n, dtype)
+    A = F.empty_blocks(dim, n, dtype)
+    R = F.empty_fields(7, n, dtype)
+
+    def step():
+        F.fdbb_flux(dim, GAMMA, U, Fg)
+        F.fdbb_flux_jacobian(dim, GAMMA, U, A)
+        F.fdbb_riemann_invariants(dim, GAMMA, U, R)
+
+    wall, ev = timed_launches(step, steps, warmup)
+    del U, Fg, A, R
+    torch.cuda.empty_cache()
+    return {"label": "3d_f64_three_launches", "n": n, "wall_ms": wall,
+            "gpoints_s": n / (wall * 1e-3) / 1e9}
+
+
+def bench_1d(steps: int, warmup: int):
+    """1D ops at N = 2^20, FP64; 32 rotating buffer sets so that the working
+    set (~1.6 GB) exceeds the 256 MB last-level cache."""
+    import torch
+    from paper_1809_09851_amd import fdbb as F
+    n = 1 << 20
+    sets = 32
+    base = device_state(1, n, 0, torch.float64)
+    Us = [base.clone() for _ in range(sets)]
+    Vs = [F.empty_fields(3, n) for _ in range(sets)]
+    Fs = [F.empty_fields(3, n) for _ in range(sets)]
+    ps = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(sets)]
+    cs = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(sets)]
+    res = {}
+    for name, bpp, fn in (
+        ("cons2prim", 48, lambda k: F.fdbb_cons2prim(1, GAMMA, Us[k], Vs[k])),
+        ("eos", 40, lambda k: F.fdbb_eos(1, GAMMA, Us[k], ps[k], cs[k])),
+        ("flux", 48, lambda k: F.fdbb_flux(1, GAMMA, Us[k], Fs[k])),
+    ):
+        ctr = [0]
+
+        def step():
+            fn(ctr[0] % sets)
+            ctr[0] += 1
+
+        wall, ev = timed_launches(step, max(steps, sets), warmup)
+        res[name] = {"gpoints_s": round(n / (ev * 1e-3) / 1e9, 3),
+                     "achieved_gbs": round(bpp * n / (ev * 1e-3) / 1e9, 1)}
+    del Us, Vs, Fs, ps, cs
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_adjoint(steps: int, warmup: int):
+    import torch
+    from paper_1809_09851_amd import fdbb as F
+    from paper_1809_09851_amd import inputs
+    n = 1 << 22
+    res = {}
+    for dim in (2, 3):
+        K = dim + 2
+        U = device_state(dim, n, 3, torch.float64)
+        Fb = F.to_fields(torch.from_numpy(inputs.cotangent(dim, n, 3)).cuda())
+        Ub = F.empty_fields(K, n)
+        wall, ev = timed_launches(lambda: F.fdbb_flux_adjoint(dim, -1, GAMMA, U, Fb, Ub), steps, warmup)
+        res[f"{dim}d"] = {"gpoints_s": round(n / (ev * 1e-3) / 1e9, 3),
+                          "achieved_gbs": round(K * K * 8 * n / (ev * 1e-3) / 1e9, 1)}
+        del U, Fb, Ub
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_probes(steps: int, warmup: int, gib: float = 4.0):
+    """What HBM delivers to plain streaming kernels: read, write, copy."""
+    import torch
+    from paper_1809_09851_amd import fdbb as F
+    nbytes = int(gib * (1 << 30))
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    sink = torch.empty(1 << 16, dtype=torch.int64, device="cuda")
+    res = {}
+    for name, moved, fn in (("read", nbytes, lambda: F.probe_read(a, sink)),
+                            ("write", nbytes, lambda: F.probe_write(b)),
+                            ("copy", 2 * nbytes, lambda: F.probe_copy(a, b))):
+        _, ev = timed_launches(fn, steps, warmup)
+        res[name] = round(moved / (ev * 1e-3) / 1e9, 1)
+    del a, b, sink
+    torch.cuda.empty_cache()
+    return res
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=1 << 24)
+    ap.add_argument("--extras", action="store_true", help="also time the other building blocks")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args(argv)
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: every building block is pointwise and one GPU's "
+              "share of a sharded run is exactly the single-GPU kernel on N/G points; "
+              "use --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1809_09851_amd import fdbb as F
+    if not os.path.exists(F.LIBRARY):
+        import __graft_entry__
+        __graft_entry__.build()
+    F.library()
+    torch.cuda.set_device(0)
+
+    main_run = bench_fused(args.n, args.steps, args.warmup, torch.float64, "3d_f64_fused")
+    print(f"# fused 3D f64: {main_run['kernel_ms']:.3f} ms/launch, "
+          f"{main_run['achieved_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
+    achieved = main_run["achieved_gbs"]
+    traffic = measured_traffic(args.n)
+    line = {
+        "metric": METRIC,
+        "value": round(main_run["gpoints_s"], 4),
+        "unit": "Gpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_run["wall_ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "euler3d_fused_flux_jacobians_riemann", "n_points": args.n, "dim": 3,
+                   "gamma": GAMMA, "storage": "f64",
+                   "state": "rho,p~U[0.5,2], v_i~N(0,0.5^2), seed 1"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "bytes_per_point": fused_bytes(3, 8), "kernel_ms": round(main_run["kernel_ms"], 4)},
+    }
+    if args.extras:
+        ex = {}
+        f32 = bench_fused(args.n, args.steps, args.warmup, torch.float32, "3d_f32_fused")
+        ex["fused_3d_f32"] = {"gpoints_s": round(f32["kernel_gpoints_s"], 3),
+                              "achieved_gbs": round(f32["achieved_gbs"], 1),
+                              "frac": round(f32["achieved_gbs"] / HBM_PEAK_GBS, 4)}
+        sep = bench_separate(args.n, max(5, args.steps // 5), 2, torch.float64)
+        ex["three_launches_3d_f64"] = {"gpoints_s": round(sep["gpoints_s"], 3)}
+        ex["ops_1d_f64_2p20"] = bench_1d(args.steps, args.warmup)
+        ex["adjoint_f64_2p22"] = bench_adjoint(args.steps, args.warmup)
+        ex["hbm_probes_gbs"] = bench_probes(max(10, args.steps // 5), 3)
+        line["extras"] = ex
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

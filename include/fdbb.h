@@ -1,0 +1,227 @@
+/*
+ * fdbb.h -- C ABI of the MI355X (gfx950) library for the compressible-Euler
+ * building blocks of "FDBB: Fluid Dynamics Building Blocks" (Moeller,
+ * Jaeschke).  Every entry point evaluates one building block point by point
+ * over structure-of-arrays state vectors in a single pass over HBM.
+ *
+ * ---------------------------------------------------------------- notation
+ * D = dim in {1, 2, 3} space dimensions, K = D + 2 state components.
+ * Conservative state U = (rho, m_1..m_D, E): density, momentum rho v and
+ * total energy per unit volume (the paper's "rho E"; Sec. 2.2, "Variables").
+ * Primitive state V = (rho, v_1..v_D, p).  Perfect gas with adiabatic index
+ * gamma = c_p / c_v > 1 (the paper's example: 7/2 over 5/2 = 1.4).
+ *
+ * ---------------------------------------------------------------- layout
+ * A "field set" is a device base pointer plus a leading dimension ld, in
+ * elements: component k of point i is base[k * ld + i] (SoA), ld >= n.
+ * The flux tensor is N_U x N_D row-major (Sec. 2.1, "Block Expressions":
+ * row-major block storage; Sec. 2.2, "Inviscid Fluxes": the 5 x 3 block), so
+ * flux component r of direction d is field r * D + d.  Flux Jacobian blocks
+ * are point-major and row-major: entry (r, c) of A_d at point i is
+ * A[(d * ldA + i) * K * K + r * K + c].
+ *
+ * dtype selects the storage type of every array of a call: FDBB_F64 (double)
+ * or FDBB_F32 (float).  Arithmetic is FP64 in both cases; FP32 values are
+ * widened exactly on load and rounded to nearest on store.
+ *
+ * ---------------------------------------------------------------- contract
+ * Ownership: the caller owns every buffer; no entry point allocates or frees
+ * memory, except the batch plans below, which own their descriptor tables
+ * and graphs until destroyed.
+ * Streams: `stream` is a hipStream_t passed as void*, NULL for the default
+ * stream.  Calls are asynchronous: they validate on the host, enqueue one
+ * kernel on `stream` and return; results are ready when the stream reaches
+ * that point.  Only launch errors are reported, not asynchronous faults.
+ * Validation (host side, before any HIP call):
+ *   FDBB_EINVAL  dim not in {1,2,3}, gamma not finite or <= 1, unknown dtype,
+ *                n < 0, a direction out of range, a NULL required pointer
+ *                with n > 0, or ld < n;
+ *   FDBB_EALIGN  a base pointer not aligned to its element size;
+ *   FDBB_EALIAS  any overlap between an input and an output field set, or
+ *                between two outputs, except the exact in-place use (same
+ *                base, same ld) allowed for the K -> K transforms
+ *                (cons2prim, prim2cons, cons2char, char2cons).  In place,
+ *                cons2prim and prim2cons leave rho where it is and do not
+ *                store it again (Sec. 2.2, "Variables": source and
+ *                destination being the same costs no transfer of density);
+ *   FDBB_EHIP    the HIP runtime reported an error at launch
+ *                (fdbb_last_error() has its text).
+ * n == 0 returns FDBB_OK without launching.  States that are not admissible
+ * (rho <= 0, p < 0) are not errors: results follow IEEE arithmetic (NaN/Inf).
+ * All entry points are thread-safe and re-entrant.
+ */
+#ifndef FDBB_H
+#define FDBB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { FDBB_F64 = 0, FDBB_F32 = 1 } fdbb_dtype;
+
+typedef enum {
+    FDBB_OK = 0,
+    FDBB_EINVAL = 1,
+    FDBB_EALIGN = 2,
+    FDBB_EALIAS = 3,
+    FDBB_EHIP = 4,
+    FDBB_ENOMEM = 5
+} fdbb_status;
+
+/* Operation ids, used by fdbb_set_launch_config and the batch tasks. */
+typedef enum {
+    FDBB_OP_CONS2PRIM = 0,
+    FDBB_OP_PRIM2CONS = 1,
+    FDBB_OP_EOS = 2,
+    FDBB_OP_FLUX = 3,
+    FDBB_OP_FLUX_JACOBIAN = 4,
+    FDBB_OP_RIEMANN = 5,
+    FDBB_OP_CONS2CHAR = 6,
+    FDBB_OP_CHAR2CONS = 7,
+    FDBB_OP_FUSED = 8,
+    FDBB_OP_ADJOINT = 9,
+    FDBB_NUM_OPS = 10
+} fdbb_op;
+
+/* Conservative -> primitive (Sec. 2.2, "Variables", conversion figure):
+ * V = (rho, v = m / rho, p = (gamma-1)(E - rho |v|^2 / 2)).
+ * U: K input fields; V: K output fields.  V == U (same ld) converts in place. */
+int fdbb_cons2prim(int dim, double gamma, int dtype, const void *U, int64_t ldU,
+                   void *V, int64_t ldV, int64_t n, void *stream);
+
+/* Primitive -> conservative (Sec. 2.2, "Variables"):
+ * U = (rho, rho v, p / (gamma-1) + rho |v|^2 / 2).  U == V converts in place. */
+int fdbb_prim2cons(int dim, double gamma, int dtype, const void *V, int64_t ldV,
+                   void *U, int64_t ldU, int64_t n, void *stream);
+
+/* Equation of state of the perfect gas (Sec. 2.2, "Equations of state";
+ * the pressure is the p_rhoe member of the EOS prototype, p = (gamma-1) rho e):
+ * p[i] and the speed of sound c[i] = sqrt(gamma p / rho), each a single
+ * field of n elements.  Either output may be NULL (not both). */
+int fdbb_eos(int dim, double gamma, int dtype, const void *U, int64_t ldU,
+             void *p, void *c, int64_t n, void *stream);
+
+/* Inviscid flux tensor (Sec. 2.2, "Inviscid Fluxes"):
+ * F(U) = [rho v; rho v (x) v + I p; v (rho E + p)], K x D row-major:
+ * F has K * D fields, field r * D + d = component r of F_d. */
+int fdbb_flux(int dim, double gamma, int dtype, const void *U, int64_t ldU,
+              void *F, int64_t ldF, int64_t n, void *stream);
+
+/* Flux Jacobians A_d = dF_d / dU for d = 0..D-1 (Fig. 1, "flux-Jacobians";
+ * the paper leaves them unfinished, Sec. 2.2, "Inviscid Fluxes"; these are
+ * the exact analytic derivatives in conservative variables).  A holds D
+ * point-major row-major K x K blocks per point, see the layout above;
+ * ldA >= n is the per-direction block stride in points. */
+int fdbb_flux_jacobian(int dim, double gamma, int dtype, const void *U, int64_t ldU,
+                       void *A, int64_t ldA, int64_t n, void *stream);
+
+/* Riemann invariants (Fig. 1): for each direction d the pair
+ * w-_d = v_d - 2c/(gamma-1), w+_d = v_d + 2c/(gamma-1), then the entropy
+ * s = p / rho^gamma.  R has 2D + 1 fields: (w-_0, w+_0, ..., w+_{D-1}, s). */
+int fdbb_riemann_invariants(int dim, double gamma, int dtype, const void *U, int64_t ldU,
+                            void *R, int64_t ldR, int64_t n, void *stream);
+
+/* Characteristic variables of direction dir (Fig. 1; EnumForm
+ * "characteristic", Sec. 2.2, "Variables"), taken pointwise as
+ * W = (w-_dir, s, v_j for j != dir ascending, w+_dir): the invariants ordered
+ * by the eigenvalues v_dir - c, v_dir (D times), v_dir + c of A_dir.
+ * K fields in, K fields out; W == U converts in place. */
+int fdbb_cons2char(int dim, int dir, double gamma, int dtype, const void *U, int64_t ldU,
+                   void *W, int64_t ldW, int64_t n, void *stream);
+
+/* Inverse of fdbb_cons2char: v_dir = (w+ + w-)/2, c = (gamma-1)(w+ - w-)/4,
+ * rho = (c^2 / (gamma s))^(1/(gamma-1)), p = rho c^2 / gamma, then U. */
+int fdbb_char2cons(int dim, int dir, double gamma, int dtype, const void *W, int64_t ldW,
+                   void *U, int64_t ldU, int64_t n, void *stream);
+
+/* Fused pass: the flux tensor (as fdbb_flux), the flux Jacobians (as
+ * fdbb_flux_jacobian) and the Riemann invariants (as
+ * fdbb_riemann_invariants) of the same state in one pass over U.  Any of
+ * F, A, R may be NULL (not all). */
+int fdbb_euler_fused(int dim, double gamma, int dtype, const void *U, int64_t ldU,
+                     void *F, int64_t ldF, void *A, int64_t ldA, void *R, int64_t ldR,
+                     int64_t n, void *stream);
+
+/* Adjoint of the flux map: Ubar = sum_d A_d(U)^T Fbar_d (dir == -1; Fbar has
+ * the flux tensor's K * D fields) or Ubar = A_dir(U)^T Fbar (dir in [0, D);
+ * Fbar has K fields).  A_d is never formed.  Ubar has K fields. */
+int fdbb_flux_adjoint(int dim, int dir, double gamma, int dtype, const void *U, int64_t ldU,
+                      const void *Fbar, int64_t ldFbar, void *Ubar, int64_t ldUbar,
+                      int64_t n, void *stream);
+
+/* ---------------------------------------------------------------- tuning
+ * Launch configuration per (op, dim, dtype): `block` threads per workgroup
+ * (64..1024, a multiple of 64), `ppt` consecutive points per thread
+ * (1, 2 or 4) and `grid_cap` the largest grid (0 = one tile per workgroup;
+ * otherwise workgroups loop over tiles).  Returns FDBB_EINVAL for values
+ * outside these sets.  The table is process-wide. */
+int fdbb_set_launch_config(int op, int dim, int dtype, int block, int ppt, int grid_cap);
+int fdbb_get_launch_config(int op, int dim, int dtype, int *block, int *ppt, int *grid_cap);
+
+/* ---------------------------------------------------------------- batches
+ * Many independent blocks of uneven size in one persistent launch.  A task
+ * names one operation on one field-set group; its fields mean what the
+ * matching single-call entry point's arguments mean:
+ *   in0  = U (V for prim2cons, W for char2cons), in1 = Fbar (adjoint only),
+ *   out0 = V / U / p / F / A / R / W / Ubar, out1 = c (eos) or A (fused),
+ *   out2 = R (fused).  Unused pointers are NULL. */
+typedef struct {
+    int32_t op;     /* fdbb_op */
+    int32_t dim;
+    int32_t dtype;  /* fdbb_dtype */
+    int32_t dir;    /* direction for cons2char/char2cons/adjoint, else 0 */
+    double gamma;
+    int64_t n;
+    const void *in0;
+    int64_t ld_in0;
+    const void *in1;
+    int64_t ld_in1;
+    void *out0;
+    int64_t ld_out0;
+    void *out1;
+    int64_t ld_out1;
+    void *out2;
+    int64_t ld_out2;
+} fdbb_task;
+
+typedef struct fdbb_batch_plan fdbb_batch_plan;
+
+/* Create a plan for up to `capacity` tasks (>= ntasks) and load `tasks`
+ * into it.  Each task is validated as its single-call entry point would be.
+ * The plan owns a device copy of the task table, the tile prefix sums and a
+ * HIP graph holding one persistent kernel with `grid` workgroups of `block`
+ * threads (grid 0 picks one sized to the device), `ppt` points per thread.
+ * Tasks that overlap one another's outputs are rejected (FDBB_EALIAS). */
+int fdbb_batch_plan_create(const fdbb_task *tasks, int ntasks, int capacity, int block,
+                           int ppt, int grid, fdbb_batch_plan **plan);
+
+/* Replace the task list (ntasks <= capacity); stream-ordered on `stream`:
+ * the upload happens before any later fdbb_batch_exec on the same stream. */
+int fdbb_batch_plan_update(fdbb_batch_plan *plan, const fdbb_task *tasks, int ntasks,
+                           void *stream);
+
+/* Run the plan's persistent launch on `stream`: use_graph != 0 replays the
+ * captured HIP graph, 0 launches the same kernel directly. */
+int fdbb_batch_exec(fdbb_batch_plan *plan, void *stream, int use_graph);
+
+/* Total points and tiles of the current task list (either may be NULL). */
+int fdbb_batch_plan_info(const fdbb_batch_plan *plan, int64_t *points, int64_t *tiles);
+
+/* Free the plan (waits for nothing: the caller must make sure no launch of
+ * it is still running). */
+int fdbb_batch_plan_destroy(fdbb_batch_plan *plan);
+
+/* ---------------------------------------------------------------- misc */
+const char *fdbb_status_string(int status);
+/* Text of the last error reported on the calling thread ("" if none). */
+const char *fdbb_last_error(void);
+/* Library version, major * 10000 + minor * 100 + patch. */
+int fdbb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDBB_H */

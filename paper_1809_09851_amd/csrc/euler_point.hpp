@@ -1,0 +1,172 @@
+// Per-point algebra of the compressible-Euler building blocks, FP64 in
+// registers.  Everything here is a __device__ inline function of one point;
+// the tile code in euler_tiles.hpp feeds it from SoA loads and writes its
+// results out.
+//
+// Conservative state U = (rho, m_1..m_D, E) with E the total energy per unit
+// volume (Sec. 2.2, "Variables"); perfect gas with gamma = c_p / c_v.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdbb {
+
+// Constants derived from gamma once per call, on the host, in FP64, so that
+// no kernel divides by (gamma - 1).
+struct Gas {
+    double gamma;        // c_p / c_v
+    double g1;           // gamma - 1
+    double half_g1;      // (gamma - 1) / 2
+    double inv_g1;       // 1 / (gamma - 1)
+    double two_inv_g1;   // 2 / (gamma - 1)
+    double quarter_g1;   // (gamma - 1) / 4
+    double inv_gamma;    // 1 / gamma
+};
+
+// Shared sub-expressions of one conservative state, computed once and reused
+// by every building block of the point.
+template <int D>
+struct State {
+    double rho, rinv, E, p;
+    double m[D];
+    double v[D];
+    double q;  // |v|^2
+};
+
+template <int D>
+__device__ __forceinline__ State<D> make_state(const Gas &g, const double *u)
+{
+    State<D> s;
+    s.rho = u[0];
+    s.rinv = 1.0 / u[0];
+    s.E = u[D + 1];
+    double q = 0.0, mv = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        s.m[k] = u[1 + k];
+        s.v[k] = s.m[k] * s.rinv;
+        q += s.v[k] * s.v[k];
+        mv += s.m[k] * s.v[k];  // rho |v|^2
+    }
+    s.q = q;
+    // p = (gamma - 1)(E - rho |v|^2 / 2): the pressure of the perfect gas.
+    s.p = g.g1 * (s.E - 0.5 * mv);
+    return s;
+}
+
+template <int D>
+__device__ __forceinline__ double sound_speed(const Gas &g, const State<D> &s)
+{
+    return sqrt(g.gamma * s.p * s.rinv);
+}
+
+// Primitive state V = (rho, v, p).
+template <int D>
+__device__ __forceinline__ void to_primitive(const State<D> &s, double *out)
+{
+    out[0] = s.rho;
+#pragma unroll
+    for (int k = 0; k < D; ++k) out[1 + k] = s.v[k];
+    out[D + 1] = s.p;
+}
+
+// Conservative state from primitive V = (rho, v, p):
+// m = rho v, E = p / (gamma - 1) + rho |v|^2 / 2.
+template <int D>
+__device__ __forceinline__ void from_primitive(const Gas &g, const double *vp, double *out)
+{
+    const double rho = vp[0];
+    double q = 0.0;
+    out[0] = rho;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        out[1 + k] = rho * vp[1 + k];
+        q += vp[1 + k] * vp[1 + k];
+    }
+    out[D + 1] = vp[D + 1] * g.inv_g1 + 0.5 * rho * q;
+}
+
+// Component r of the inviscid flux in direction d: F_d = (m_d,
+// m_i v_d + delta_id p, v_d (E + p)).
+template <int D>
+__device__ __forceinline__ double flux_entry(const State<D> &s, int r, int d)
+{
+    if (r == 0) return s.m[d];
+    if (r == D + 1) return s.v[d] * (s.E + s.p);
+    const int i = r - 1;
+    const double mom = s.m[i] * s.v[d];
+    return (i == d) ? mom + s.p : mom;
+}
+
+// Entry (r, c) of A_d = dF_d/dU, the derivative of the flux above through
+// dp/drho = phi, dp/dm_j = -(gamma-1) v_j, dp/dE = gamma - 1, with
+// phi = (gamma-1)|v|^2/2 and the total enthalpy H = (E + p)/rho:
+//   row 0       : e_{1+d}
+//   row 1+i     : [delta_id phi - v_i v_d,
+//                  delta_ij v_d + delta_jd v_i - (gamma-1) delta_id v_j,
+//                  (gamma-1) delta_id]
+//   row D+1     : [v_d (phi - H), delta_jd H - (gamma-1) v_j v_d, gamma v_d]
+// r, c and d are compile-time constants after unrolling, so every branch
+// folds away.
+template <int D>
+__device__ __forceinline__ double jacobian_entry(const Gas &g, const State<D> &s, double phi,
+                                                 double H, int d, int r, int c)
+{
+    constexpr int K = D + 2;
+    if (r == 0) return (c == 1 + d) ? 1.0 : 0.0;
+    if (r == K - 1) {
+        if (c == 0) return s.v[d] * (phi - H);
+        if (c == K - 1) return g.gamma * s.v[d];
+        const int j = c - 1;
+        const double t = -g.g1 * s.v[j] * s.v[d];
+        return (j == d) ? t + H : t;
+    }
+    const int i = r - 1;
+    if (c == 0) return (i == d) ? phi - s.v[i] * s.v[d] : -s.v[i] * s.v[d];
+    if (c == K - 1) return (i == d) ? g.g1 : 0.0;
+    const int j = c - 1;
+    double t = 0.0;
+    if (i == j) t += s.v[d];
+    if (j == d) t += s.v[i];
+    if (i == d) t -= g.g1 * s.v[j];
+    return t;
+}
+
+// Entropy s = p / rho^gamma.
+template <int D>
+__device__ __forceinline__ double entropy(const Gas &g, const State<D> &s)
+{
+    return s.p * pow(s.rho, -g.gamma);
+}
+
+// Adjoint contribution of direction d: ubar += A_d^T fb, where fb = (a,
+// b_1..b_D, e) is the cotangent of F_d.  Written out from the transposed
+// Jacobian above with bv = b . v:
+//   ubar_0    += phi b_d - v_d bv + e v_d (phi - H)
+//   ubar_1+j  += delta_jd (a + bv + e H) + b_j v_d - (gamma-1) v_j (b_d + e v_d)
+//   ubar_D+1  += (gamma-1) b_d + gamma v_d e
+template <int D>
+__device__ __forceinline__ void adjoint_accumulate(const Gas &g, const State<D> &s, double phi,
+                                                   double H, int d, const double *fb,
+                                                   double *ubar)
+{
+    const double a = fb[0];
+    const double e = fb[D + 1];
+    double bv = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) bv += fb[1 + i] * s.v[i];
+    const double bd = fb[1 + d];
+    const double vd = s.v[d];
+    ubar[0] += phi * bd - vd * bv + e * vd * (phi - H);
+    const double w = g.g1 * (bd + e * vd);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        double t = fb[1 + j] * vd - w * s.v[j];
+        if (j == d) t += a + bv + e * H;
+        ubar[1 + j] += t;
+    }
+    ubar[D + 1] += g.g1 * bd + g.gamma * vd * e;
+}
+
+}  // namespace fdbb

@@ -1,0 +1,817 @@
+// C ABI of the library (declared in include/fdbb.h): host-side validation,
+// launch configuration, kernel launches on the caller's stream, and the
+// persistent batch plans with their HIP graphs.
+#include "../../include/fdbb.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fdbb_internal.hpp"
+
+using namespace fdbb;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const std::string &msg)
+{
+    g_last_error = msg;
+    return status;
+}
+
+int fail_hip(hipError_t e, const char *what)
+{
+    return fail(FDBB_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t elem_size(int dtype) { return dtype == FDBB_F64 ? 8 : 4; }
+
+// ------------------------------------------------------------ device facts
+
+struct DeviceInfo {
+    int cus = 0;
+    size_t lds_max = 0;
+};
+
+std::mutex g_dev_mutex;
+DeviceInfo g_dev[64];
+
+int device_info(DeviceInfo *out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(FDBB_EHIP, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_dev_mutex);
+    if (g_dev[dev].cus == 0) {
+        int cus = 0, lds = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return fail_hip(e, "hipDeviceGetAttribute");
+        e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e != hipSuccess) return fail_hip(e, "hipDeviceGetAttribute");
+        g_dev[dev].cus = cus;
+        g_dev[dev].lds_max = (size_t)lds;
+    }
+    *out = g_dev[dev];
+    return FDBB_OK;
+}
+
+// ------------------------------------------------------------ launch table
+
+struct Config {
+    int block;
+    int ppt;
+    int grid_cap;
+};
+
+std::atomic<uint64_t> g_cfg[FDBB_NUM_OPS][3][2];
+std::once_flag g_cfg_once;
+
+uint64_t pack(const Config &c)
+{
+    return (uint64_t)(uint16_t)c.block | ((uint64_t)(uint8_t)c.ppt << 16) |
+           ((uint64_t)(uint32_t)c.grid_cap << 32);
+}
+
+Config unpack(uint64_t v)
+{
+    Config c;
+    c.block = (int)(v & 0xffff);
+    c.ppt = (int)((v >> 16) & 0xff);
+    c.grid_cap = (int)(uint32_t)(v >> 32);
+    return c;
+}
+
+void init_configs()
+{
+    for (int op = 0; op < FDBB_NUM_OPS; ++op)
+        for (int d = 0; d < 3; ++d)
+            for (int t = 0; t < 2; ++t) {
+                Config c;
+                const bool jac = (op == FDBB_OP_FLUX_JACOBIAN || op == FDBB_OP_FUSED);
+                c.block = 256;
+                c.ppt = jac ? 1 : (t == FDBB_F64 ? 2 : 4);
+                c.grid_cap = 0;
+                g_cfg[op][d][t].store(pack(c));
+            }
+}
+
+Config get_config(int op, int dim, int dtype)
+{
+    std::call_once(g_cfg_once, init_configs);
+    return unpack(g_cfg[op][dim - 1][dtype].load(std::memory_order_relaxed));
+}
+
+bool config_ok(int block, int ppt, int grid_cap)
+{
+    return block >= 64 && block <= 1024 && block % 64 == 0 && (ppt == 1 || ppt == 2 || ppt == 4) &&
+           grid_cap >= 0;
+}
+
+// ------------------------------------------------------------ validation
+
+// Byte range of a field set: `fields` rows of stride ld, the last one n long,
+// each element `unit` elements of T wide (K*K for Jacobian blocks).
+struct Range {
+    uintptr_t lo, hi;
+    bool input;
+    const void *base;
+    int64_t ld;
+    int task;
+};
+
+Range field_range(const void *base, int64_t ld, int64_t fields, int64_t n, int64_t unit, size_t es,
+                  bool input, int task = 0)
+{
+    Range r;
+    r.lo = (uintptr_t)base;
+    r.hi = r.lo + (uintptr_t)(((fields - 1) * ld + n) * unit) * es;
+    r.input = input;
+    r.base = base;
+    r.ld = ld;
+    r.task = task;
+    return r;
+}
+
+bool overlap(const Range &a, const Range &b) { return a.lo < b.hi && b.lo < a.hi; }
+
+int check_common(int dim, double gamma, int dtype, int64_t n)
+{
+    if (dim < 1 || dim > 3) return fail(FDBB_EINVAL, "dim must be 1, 2 or 3");
+    if (!std::isfinite(gamma) || !(gamma > 1.0)) return fail(FDBB_EINVAL, "gamma must be finite and > 1");
+    if (dtype != FDBB_F64 && dtype != FDBB_F32) return fail(FDBB_EINVAL, "unknown dtype");
+    if (n < 0) return fail(FDBB_EINVAL, "n must be >= 0");
+    return FDBB_OK;
+}
+
+Gas make_gas(double gamma)
+{
+    Gas g;
+    g.gamma = gamma;
+    g.g1 = gamma - 1.0;
+    g.half_g1 = 0.5 * (gamma - 1.0);
+    g.inv_g1 = 1.0 / (gamma - 1.0);
+    g.two_inv_g1 = 2.0 / (gamma - 1.0);
+    g.quarter_g1 = 0.25 * (gamma - 1.0);
+    g.inv_gamma = 1.0 / gamma;
+    return g;
+}
+
+// Everything one launch needs, built and validated on the host.
+struct Call {
+    int op = 0, dim = 0, dtype = 0;
+    Args a{};
+    std::vector<Range> ranges;  // for alias checks
+    bool inplace_ok = false;    // K -> K transform
+    size_t unit_out1 = 1;       // elements per point of out1 (K*K for Jacobian blocks)
+};
+
+// Register one field set: checks NULL, ld and alignment.
+int add_fields(Call &c, const void *base, int64_t ld, int64_t fields, int64_t unit, bool input,
+               bool required, const char *name)
+{
+    const int64_t n = c.a.n;
+    const size_t es = elem_size(c.dtype);
+    if (base == nullptr) {
+        if (required && n > 0) return fail(FDBB_EINVAL, std::string(name) + " must not be NULL");
+        return FDBB_OK;
+    }
+    if (fields > 1 && ld < n) return fail(FDBB_EINVAL, std::string("ld of ") + name + " must be >= n");
+    if ((uintptr_t)base % es != 0)
+        return fail(FDBB_EALIGN, std::string(name) + " is not aligned to its element size");
+    if (n > 0) c.ranges.push_back(field_range(base, fields > 1 ? ld : 0, fields, n, unit, es, input));
+    return FDBB_OK;
+}
+
+int check_alias(const Call &c)
+{
+    const auto &R = c.ranges;
+    for (size_t i = 0; i < R.size(); ++i)
+        for (size_t j = i + 1; j < R.size(); ++j) {
+            if (R[i].input && R[j].input) continue;
+            if (!overlap(R[i], R[j])) continue;
+            const bool exact = R[i].base == R[j].base && R[i].ld == R[j].ld && R[i].input != R[j].input;
+            if (exact && c.inplace_ok) continue;
+            return fail(FDBB_EALIAS, "input and output field sets overlap");
+        }
+    return FDBB_OK;
+}
+
+// 16-byte access is allowed when every base is 16-byte aligned and every row
+// stride is a multiple of 16 bytes.
+bool vector_ok(const Call &c)
+{
+    const size_t es = elem_size(c.dtype);
+    const void *bases[5] = {c.a.in0, c.a.in1, c.a.out0, c.a.out1, c.a.out2};
+    const int64_t lds[5] = {c.a.ld_in0, c.a.ld_in1, c.a.ld_out0, c.a.ld_out1, c.a.ld_out2};
+    for (int k = 0; k < 5; ++k) {
+        if (!bases[k]) continue;
+        if ((uintptr_t)bases[k] % 16 != 0) return false;
+        const size_t unit = (k == 3) ? c.unit_out1 : 1;
+        if (((size_t)lds[k] * unit * es) % 16 != 0) return false;
+    }
+    return true;
+}
+
+int family_of(int op)
+{
+    switch (op) {
+    case FDBB_OP_CONS2PRIM: return kFamCons2Prim;
+    case FDBB_OP_PRIM2CONS: return kFamPrim2Cons;
+    case FDBB_OP_EOS: return kFamEos;
+    case FDBB_OP_FLUX: return kFamFlux;
+    case FDBB_OP_RIEMANN: return kFamRiemann;
+    case FDBB_OP_CONS2CHAR: return kFamCons2Char;
+    case FDBB_OP_CHAR2CONS: return kFamChar2Cons;
+    case FDBB_OP_FLUX_JACOBIAN:
+    case FDBB_OP_FUSED: return kFamFused;
+    case FDBB_OP_ADJOINT: return kFamAdjoint;
+    default: return -1;
+    }
+}
+
+const void *kernel_for(int op, int dim, int dtype, int ppt)
+{
+    const int fam = family_of(op);
+    switch (fam) {
+    case kFamCons2Prim:
+    case kFamPrim2Cons:
+    case kFamEos:
+    case kFamFlux:
+    case kFamRiemann: return kernel_pointwise(fam, dim, dtype, ppt);
+    case kFamCons2Char:
+    case kFamChar2Cons: return kernel_char(fam, dim, dtype, ppt);
+    case kFamFused: return kernel_fused(dim, dtype, ppt);
+    case kFamAdjoint: return kernel_adjoint(dim, dtype, ppt);
+    default: return nullptr;
+    }
+}
+
+size_t lds_bytes(int op, int dim, int dtype, int block, int ppt)
+{
+    if (family_of(op) != kFamFused) return 0;
+    // Jacobian blocks only need staging when they are written.
+    const size_t K = (size_t)dim + 2;
+    return (size_t)block * ppt * K * K * elem_size(dtype);
+}
+
+std::mutex g_attr_mutex;
+
+int set_lds_attr(const void *fn, size_t lds, const DeviceInfo &dev)
+{
+    if (lds <= 65536) return FDBB_OK;
+    if (lds > dev.lds_max) return fail(FDBB_EINVAL, "launch configuration needs more LDS than a workgroup may use");
+    std::lock_guard<std::mutex> lock(g_attr_mutex);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return fail_hip(e, "hipFuncSetAttribute");
+    return FDBB_OK;
+}
+
+int launch(Call &c, void *stream)
+{
+    if (c.a.n == 0) return FDBB_OK;
+    int rc = check_alias(c);
+    if (rc) return rc;
+    if (vector_ok(c)) c.a.flags |= kFlagVector;
+
+    const Config cfg = get_config(c.op, c.dim, c.dtype);
+    const void *fn = kernel_for(c.op, c.dim, c.dtype, cfg.ppt);
+    if (!fn) return fail(FDBB_EINVAL, "no kernel for this configuration");
+    DeviceInfo dev;
+    rc = device_info(&dev);
+    if (rc) return rc;
+    const bool needs_lds = (c.op == FDBB_OP_FLUX_JACOBIAN) || (c.op == FDBB_OP_FUSED && c.a.out1);
+    const size_t lds = needs_lds ? lds_bytes(c.op, c.dim, c.dtype, cfg.block, cfg.ppt) : 0;
+    rc = set_lds_attr(fn, lds, dev);
+    if (rc) return rc;
+
+    const int64_t tile_pts = (int64_t)cfg.block * cfg.ppt;
+    int64_t ntiles = (c.a.n + tile_pts - 1) / tile_pts;
+    int64_t grid = ntiles;
+    if (cfg.grid_cap > 0 && grid > cfg.grid_cap) grid = cfg.grid_cap;
+    if (grid > 0x7fffffff) grid = 0x7fffffff;
+    void *args[] = {&c.a, &ntiles};
+    hipError_t e = hipLaunchKernel(fn, dim3((unsigned)grid), dim3((unsigned)cfg.block), args, lds,
+                                   (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "kernel launch");
+    return FDBB_OK;
+}
+
+int begin(Call &c, int op, int dim, double gamma, int dtype, int64_t n)
+{
+    int rc = check_common(dim, gamma, dtype, n);
+    if (rc) return rc;
+    c.op = op;
+    c.dim = dim;
+    c.dtype = dtype;
+    c.a.n = n;
+    c.a.gas = make_gas(gamma);
+    g_last_error.clear();
+    return FDBB_OK;
+}
+
+// Fills c for any op from the task-style argument list; shared by the
+// single-call entry points and the batch plans.
+int build_call(Call &c, const fdbb_task &t)
+{
+    int rc = begin(c, t.op, t.dim, t.gamma, t.dtype, t.n);
+    if (rc) return rc;
+    const int D = t.dim, K = D + 2;
+    Args &a = c.a;
+    a.dir = 0;
+    switch (t.op) {
+    case FDBB_OP_CONS2PRIM:
+    case FDBB_OP_PRIM2CONS:
+    case FDBB_OP_CONS2CHAR:
+    case FDBB_OP_CHAR2CONS: {
+        if (t.op == FDBB_OP_CONS2CHAR || t.op == FDBB_OP_CHAR2CONS) {
+            if (t.dir < 0 || t.dir >= D) return fail(FDBB_EINVAL, "dir out of range");
+            a.dir = t.dir;
+        }
+        c.inplace_ok = true;
+        a.in0 = t.in0, a.ld_in0 = t.ld_in0, a.out0 = t.out0, a.ld_out0 = t.ld_out0;
+        if ((rc = add_fields(c, t.in0, t.ld_in0, K, 1, true, true, "input"))) return rc;
+        if ((rc = add_fields(c, t.out0, t.ld_out0, K, 1, false, true, "output"))) return rc;
+        if (t.in0 == t.out0 && t.ld_in0 == t.ld_out0 &&
+            (t.op == FDBB_OP_CONS2PRIM || t.op == FDBB_OP_PRIM2CONS))
+            a.flags |= kFlagInPlace;
+        break;
+    }
+    case FDBB_OP_EOS:
+        if (!t.out0 && !t.out1 && t.n > 0) return fail(FDBB_EINVAL, "p and c must not both be NULL");
+        a.in0 = t.in0, a.ld_in0 = t.ld_in0, a.out0 = t.out0, a.out1 = t.out1;
+        if ((rc = add_fields(c, t.in0, t.ld_in0, K, 1, true, true, "U"))) return rc;
+        if ((rc = add_fields(c, t.out0, 0, 1, 1, false, false, "p"))) return rc;
+        if ((rc = add_fields(c, t.out1, 0, 1, 1, false, false, "c"))) return rc;
+        break;
+    case FDBB_OP_FLUX:
+        a.in0 = t.in0, a.ld_in0 = t.ld_in0, a.out0 = t.out0, a.ld_out0 = t.ld_out0;
+        if ((rc = add_fields(c, t.in0, t.ld_in0, K, 1, true, true, "U"))) return rc;
+        if ((rc = add_fields(c, t.out0, t.ld_out0, (int64_t)K * D, 1, false, true, "F"))) return rc;
+        break;
+    case FDBB_OP_RIEMANN:
+        a.in0 = t.in0, a.ld_in0 = t.ld_in0, a.out0 = t.out0, a.ld_out0 = t.ld_out0;
+        if ((rc = add_fields(c, t.in0, t.ld_in0, K, 1, true, true, "U"))) return rc;
+        if ((rc = add_fields(c, t.out0, t.ld_out0, 2 * D + 1, 1, false, true, "R"))) return rc;
+        break;
+    case FDBB_OP_FLUX_JACOBIAN:
+        // The Jacobian blocks travel in out1 of the fused kernel.
+        c.unit_out1 = (size_t)K * K;
+        a.in0 = t.in0, a.ld_in0 = t.ld_in0, a.out1 = t.out0, a.ld_out1 = t.ld_out0;
+        if ((rc = add_fields(c, t.in0, t.ld_in0, K, 1, true, true, "U"))) return rc;
+        if ((rc = add_fields(c, t.out0, t.ld_out0, D, (int64_t)K * K, false, true, "A"))) return rc;
+        break;
+    case FDBB_OP_FUSED:
+        if (!t.out0 && !t.out1 && !t.out2 && t.n > 0) return fail(FDBB_EINVAL, "F, A and R must not all be NULL");
+        c.unit_out1 = (size_t)K * K;
+        a.in0 = t.in0, a.ld_in0 = t.ld_in0;
+        a.out0 = t.out0, a.ld_out0 = t.ld_out0;
+        a.out1 = t.out1, a.ld_out1 = t.ld_out1;
+        a.out2 = t.out2, a.ld_out2 = t.ld_out2;
+        if ((rc = add_fields(c, t.in0, t.ld_in0, K, 1, true, true, "U"))) return rc;
+        if ((rc = add_fields(c, t.out0, t.ld_out0, (int64_t)K * D, 1, false, false, "F"))) return rc;
+        if ((rc = add_fields(c, t.out1, t.ld_out1, D, (int64_t)K * K, false, false, "A"))) return rc;
+        if ((rc = add_fields(c, t.out2, t.ld_out2, 2 * D + 1, 1, false, false, "R"))) return rc;
+        break;
+    case FDBB_OP_ADJOINT:
+        if (t.dir < -1 || t.dir >= D) return fail(FDBB_EINVAL, "dir out of range");
+        a.dir = t.dir;
+        a.in0 = t.in0, a.ld_in0 = t.ld_in0, a.in1 = t.in1, a.ld_in1 = t.ld_in1;
+        a.out0 = t.out0, a.ld_out0 = t.ld_out0;
+        if ((rc = add_fields(c, t.in0, t.ld_in0, K, 1, true, true, "U"))) return rc;
+        if ((rc = add_fields(c, t.in1, t.ld_in1, t.dir < 0 ? (int64_t)K * D : K, 1, true, true, "Fbar")))
+            return rc;
+        if ((rc = add_fields(c, t.out0, t.ld_out0, K, 1, false, true, "Ubar"))) return rc;
+        break;
+    default: return fail(FDBB_EINVAL, "unknown op");
+    }
+    return FDBB_OK;
+}
+
+fdbb_task make_task(int op, int dim, int dir, double gamma, int dtype, int64_t n)
+{
+    fdbb_task t;
+    std::memset(&t, 0, sizeof(t));
+    t.op = op;
+    t.dim = dim;
+    t.dir = dir;
+    t.gamma = gamma;
+    t.dtype = dtype;
+    t.n = n;
+    return t;
+}
+
+int run(const fdbb_task &t, void *stream)
+{
+    Call c;
+    int rc = build_call(c, t);
+    if (rc) return rc;
+    return launch(c, stream);
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+
+extern "C" {
+
+int fdbb_cons2prim(int dim, double gamma, int dtype, const void *U, int64_t ldU, void *V, int64_t ldV,
+                   int64_t n, void *stream)
+{
+    fdbb_task t = make_task(FDBB_OP_CONS2PRIM, dim, 0, gamma, dtype, n);
+    t.in0 = U, t.ld_in0 = ldU, t.out0 = V, t.ld_out0 = ldV;
+    return run(t, stream);
+}
+
+int fdbb_prim2cons(int dim, double gamma, int dtype, const void *V, int64_t ldV, void *U, int64_t ldU,
+                   int64_t n, void *stream)
+{
+    fdbb_task t = make_task(FDBB_OP_PRIM2CONS, dim, 0, gamma, dtype, n);
+    t.in0 = V, t.ld_in0 = ldV, t.out0 = U, t.ld_out0 = ldU;
+    return run(t, stream);
+}
+
+int fdbb_eos(int dim, double gamma, int dtype, const void *U, int64_t ldU, void *p, void *c, int64_t n,
+             void *stream)
+{
+    fdbb_task t = make_task(FDBB_OP_EOS, dim, 0, gamma, dtype, n);
+    t.in0 = U, t.ld_in0 = ldU, t.out0 = p, t.out1 = c;
+    return run(t, stream);
+}
+
+int fdbb_flux(int dim, double gamma, int dtype, const void *U, int64_t ldU, void *F, int64_t ldF, int64_t n,
+              void *stream)
+{
+    fdbb_task t = make_task(FDBB_OP_FLUX, dim, 0, gamma, dtype, n);
+    t.in0 = U, t.ld_in0 = ldU, t.out0 = F, t.ld_out0 = ldF;
+    return run(t, stream);
+}
+
+int fdbb_flux_jacobian(int dim, double gamma, int dtype, const void *U, int64_t ldU, void *A, int64_t ldA,
+                       int64_t n, void *stream)
+{
+    fdbb_task t = make_task(FDBB_OP_FLUX_JACOBIAN, dim, 0, gamma, dtype, n);
+    t.in0 = U, t.ld_in0 = ldU, t.out0 = A, t.ld_out0 = ldA;
+    return run(t, stream);
+}
+
+int fdbb_riemann_invariants(int dim, double gamma, int dtype, const void *U, int64_t ldU, void *R,
+                            int64_t ldR, int64_t n, void *stream)
+{
+    fdbb_task t = make_task(FDBB_OP_RIEMANN, dim, 0, gamma, dtype, n);
+    t.in0 = U, t.ld_in0 = ldU, t.out0 = R, t.ld_out0 = ldR;
+    return run(t, stream);
+}
+
+int fdbb_cons2char(int dim, int dir, double gamma, int dtype, const void *U, int64_t ldU, void *W,
+                   int64_t ldW, int64_t n, void *stream)
+{
+    fdbb_task t = make_task(FDBB_OP_CONS2CHAR, dim, dir, gamma, dtype, n);
+    t.in0 = U, t.ld_in0 = ldU, t.out0 = W, t.ld_out0 = ldW;
+    return run(t, stream);
+}
+
+int fdbb_char2cons(int dim, int dir, double gamma, int dtype, const void *W, int64_t ldW, void *U,
+                   int64_t ldU, int64_t n, void *stream)
+{
+    fdbb_task t = make_task(FDBB_OP_CHAR2CONS, dim, dir, gamma, dtype, n);
+    t.in0 = W, t.ld_in0 = ldW, t.out0 = U, t.ld_out0 = ldU;
+    return run(t, stream);
+}
+
+int fdbb_euler_fused(int dim, double gamma, int dtype, const void *U, int64_t ldU, void *F, int64_t ldF,
+                     void *A, int64_t ldA, void *R, int64_t ldR, int64_t n, void *stream)
+{
+    fdbb_task t = make_task(FDBB_OP_FUSED, dim, 0, gamma, dtype, n);
+    t.in0 = U, t.ld_in0 = ldU;
+    t.out0 = F, t.ld_out0 = ldF;
+    t.out1 = A, t.ld_out1 = ldA;
+    t.out2 = R, t.ld_out2 = ldR;
+    return run(t, stream);
+}
+
+int fdbb_flux_adjoint(int dim, int dir, double gamma, int dtype, const void *U, int64_t ldU,
+                      const void *Fbar, int64_t ldFbar, void *Ubar, int64_t ldUbar, int64_t n, void *stream)
+{
+    fdbb_task t = make_task(FDBB_OP_ADJOINT, dim, dir, gamma, dtype, n);
+    t.in0 = U, t.ld_in0 = ldU, t.in1 = Fbar, t.ld_in1 = ldFbar, t.out0 = Ubar, t.ld_out0 = ldUbar;
+    return run(t, stream);
+}
+
+int fdbb_set_launch_config(int op, int dim, int dtype, int block, int ppt, int grid_cap)
+{
+    if (op < 0 || op >= FDBB_NUM_OPS || dim < 1 || dim > 3 || (dtype != FDBB_F64 && dtype != FDBB_F32))
+        return fail(FDBB_EINVAL, "unknown op, dim or dtype");
+    if (!config_ok(block, ppt, grid_cap)) return fail(FDBB_EINVAL, "invalid launch configuration");
+    std::call_once(g_cfg_once, init_configs);
+    Config c{block, ppt, grid_cap};
+    g_cfg[op][dim - 1][dtype].store(pack(c));
+    return FDBB_OK;
+}
+
+int fdbb_get_launch_config(int op, int dim, int dtype, int *block, int *ppt, int *grid_cap)
+{
+    if (op < 0 || op >= FDBB_NUM_OPS || dim < 1 || dim > 3 || (dtype != FDBB_F64 && dtype != FDBB_F32))
+        return fail(FDBB_EINVAL, "unknown op, dim or dtype");
+    const Config c = get_config(op, dim, dtype);
+    if (block) *block = c.block;
+    if (ppt) *ppt = c.ppt;
+    if (grid_cap) *grid_cap = c.grid_cap;
+    return FDBB_OK;
+}
+
+const char *fdbb_status_string(int status)
+{
+    switch (status) {
+    case FDBB_OK: return "ok";
+    case FDBB_EINVAL: return "invalid argument";
+    case FDBB_EALIGN: return "misaligned pointer";
+    case FDBB_EALIAS: return "input and output overlap";
+    case FDBB_EHIP: return "HIP runtime error";
+    case FDBB_ENOMEM: return "out of memory";
+    default: return "unknown status";
+    }
+}
+
+const char *fdbb_last_error(void) { return g_last_error.c_str(); }
+
+int fdbb_version(void) { return 100; }
+
+}  // extern "C"
+
+// ================================================================ batches
+
+struct fdbb_batch_plan {
+    int device = 0;
+    int capacity = 0;
+    int ntasks = 0;
+    int block = 256;
+    int ppt = 1;
+    int grid = 0;
+    size_t lds = 0;
+    int64_t points = 0;
+    int64_t tiles = 0;
+    const void *kernel = nullptr;
+    unsigned char *dev = nullptr;   // [header 2 x int64][prefix cap+1][tasks cap]
+    unsigned char *host = nullptr;  // pinned staging copy of the same layout
+    size_t bytes = 0;
+    hipEvent_t uploaded = nullptr;  // the last upload has left the staging copy
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    int64_t *header(unsigned char *base) const { return reinterpret_cast<int64_t *>(base); }
+    int64_t *prefix(unsigned char *base) const { return reinterpret_cast<int64_t *>(base) + 2; }
+    TaskDev *tasks(unsigned char *base) const
+    {
+        size_t off = (2 + (size_t)capacity + 1) * sizeof(int64_t);
+        off = (off + 63) & ~(size_t)63;
+        return reinterpret_cast<TaskDev *>(base + off);
+    }
+};
+
+namespace {
+
+size_t plan_bytes(int capacity)
+{
+    size_t off = (2 + (size_t)capacity + 1) * sizeof(int64_t);
+    off = (off + 63) & ~(size_t)63;
+    return off + (size_t)capacity * sizeof(TaskDev);
+}
+
+// Validate tasks and fill the plan's pinned staging copy.
+int stage_tasks(fdbb_batch_plan *p, const fdbb_task *tasks, int ntasks)
+{
+    if (ntasks < 0 || ntasks > p->capacity) return fail(FDBB_EINVAL, "ntasks exceeds the plan capacity");
+    if (ntasks > 0 && !tasks) return fail(FDBB_EINVAL, "tasks must not be NULL");
+    std::vector<Call> calls((size_t)ntasks);
+    std::vector<Range> all;
+    size_t need_lds = 0;
+    for (int b = 0; b < ntasks; ++b) {
+        int rc = build_call(calls[b], tasks[b]);
+        if (rc) return fail(rc, "task " + std::to_string(b) + ": " + g_last_error);
+        rc = check_alias(calls[b]);
+        if (rc) return fail(rc, "task " + std::to_string(b) + ": " + g_last_error);
+        if (vector_ok(calls[b])) calls[b].a.flags |= kFlagVector;
+        const bool jac = tasks[b].op == FDBB_OP_FLUX_JACOBIAN || (tasks[b].op == FDBB_OP_FUSED && tasks[b].out1);
+        if (jac) need_lds = std::max(need_lds, lds_bytes(tasks[b].op, tasks[b].dim, tasks[b].dtype, p->block, p->ppt));
+        for (Range r : calls[b].ranges) {
+            r.task = b;
+            all.push_back(r);
+        }
+    }
+    if (need_lds > p->lds) return fail(FDBB_EINVAL, "tasks need more LDS than the plan was created with");
+    // Across tasks: no output may overlap another task's input or output.
+    std::sort(all.begin(), all.end(), [](const Range &x, const Range &y) { return x.lo < y.lo; });
+    for (size_t i = 0; i < all.size(); ++i) {
+        for (size_t j = i + 1; j < all.size() && all[j].lo < all[i].hi; ++j) {
+            if (all[i].task == all[j].task) continue;
+            if (all[i].input && all[j].input) continue;
+            return fail(FDBB_EALIAS, "tasks " + std::to_string(all[i].task) + " and " +
+                                         std::to_string(all[j].task) + " overlap");
+        }
+    }
+    // The previous upload must have consumed the staging copy.
+    if (p->uploaded) {
+        hipError_t e = hipEventSynchronize(p->uploaded);
+        if (e != hipSuccess) return fail_hip(e, "hipEventSynchronize");
+    }
+    int64_t *hdr = p->header(p->host);
+    int64_t *pre = p->prefix(p->host);
+    TaskDev *td = p->tasks(p->host);
+    const int64_t tile_pts = (int64_t)p->block * p->ppt;
+    int64_t tiles = 0, points = 0;
+    for (int b = 0; b < ntasks; ++b) {
+        pre[b] = tiles;
+        tiles += (tasks[b].n + tile_pts - 1) / tile_pts;
+        points += tasks[b].n;
+        td[b].a = calls[b].a;
+        td[b].op = tasks[b].op;
+        td[b].dim = tasks[b].dim;
+        td[b].dtype = tasks[b].dtype;
+        td[b].pad = 0;
+    }
+    pre[ntasks] = tiles;
+    hdr[0] = ntasks;
+    hdr[1] = tiles;
+    p->ntasks = ntasks;
+    p->tiles = tiles;
+    p->points = points;
+    return FDBB_OK;
+}
+
+int upload(fdbb_batch_plan *p, hipStream_t s)
+{
+    hipError_t e = hipMemcpyAsync(p->dev, p->host, p->bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync");
+    e = hipEventRecord(p->uploaded, s);
+    if (e != hipSuccess) return fail_hip(e, "hipEventRecord");
+    return FDBB_OK;
+}
+
+int launch_plan(fdbb_batch_plan *p, hipStream_t s)
+{
+    unsigned char *d = p->dev;
+    const TaskDev *tasks = p->tasks(d);
+    const int64_t *prefix = p->prefix(d);
+    const int64_t *header = p->header(d);
+    void *args[] = {&tasks, &prefix, &header};
+    hipError_t e = hipLaunchKernel(p->kernel, dim3((unsigned)p->grid), dim3((unsigned)p->block), args, p->lds, s);
+    if (e != hipSuccess) return fail_hip(e, "batch kernel launch");
+    return FDBB_OK;
+}
+
+void free_plan(fdbb_batch_plan *p)
+{
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->uploaded) (void)hipEventDestroy(p->uploaded);
+    if (p->dev) (void)hipFree(p->dev);
+    if (p->host) (void)hipHostFree(p->host);
+    delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fdbb_batch_plan_create(const fdbb_task *tasks, int ntasks, int capacity, int block, int ppt, int grid,
+                           fdbb_batch_plan **plan)
+{
+    g_last_error.clear();
+    if (!plan) return fail(FDBB_EINVAL, "plan must not be NULL");
+    *plan = nullptr;
+    if (capacity < 1 || capacity < ntasks) return fail(FDBB_EINVAL, "capacity must be >= max(1, ntasks)");
+    if (!config_ok(block, ppt, grid)) return fail(FDBB_EINVAL, "invalid launch configuration");
+    if (ntasks > 0 && !tasks) return fail(FDBB_EINVAL, "tasks must not be NULL");
+    // Argument checks of every task come before any HIP call.
+    for (int b = 0; b < ntasks; ++b) {
+        Call c;
+        int rc = build_call(c, tasks[b]);
+        if (!rc) rc = check_alias(c);
+        if (rc) return fail(rc, "task " + std::to_string(b) + ": " + g_last_error);
+    }
+    DeviceInfo dev;
+    int rc = device_info(&dev);
+    if (rc) return rc;
+
+    fdbb_batch_plan *p = new fdbb_batch_plan();
+    p->capacity = capacity;
+    p->block = block;
+    p->ppt = ppt;
+    p->kernel = kernel_batch(ppt);
+    (void)hipGetDevice(&p->device);
+    // LDS for the largest Jacobian staging among the first task list.
+    size_t lds = 0;
+    for (int b = 0; b < ntasks && tasks; ++b) {
+        const bool jac = tasks[b].op == FDBB_OP_FLUX_JACOBIAN || (tasks[b].op == FDBB_OP_FUSED && tasks[b].out1);
+        if (jac && tasks[b].dim >= 1 && tasks[b].dim <= 3 && (tasks[b].dtype == 0 || tasks[b].dtype == 1))
+            lds = std::max(lds, lds_bytes(tasks[b].op, tasks[b].dim, tasks[b].dtype, block, ppt));
+    }
+    p->lds = lds;
+    if ((rc = set_lds_attr(p->kernel, lds, dev))) {
+        free_plan(p);
+        return rc;
+    }
+    p->grid = grid > 0 ? grid : dev.cus * std::max(1, 2048 / block);
+    p->bytes = plan_bytes(capacity);
+    hipError_t e = hipMalloc((void **)&p->dev, p->bytes);
+    if (e != hipSuccess) {
+        free_plan(p);
+        return fail_hip(e, "hipMalloc");
+    }
+    e = hipHostMalloc((void **)&p->host, p->bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        free_plan(p);
+        return fail_hip(e, "hipHostMalloc");
+    }
+    std::memset(p->host, 0, p->bytes);
+    e = hipEventCreateWithFlags(&p->uploaded, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        free_plan(p);
+        return fail_hip(e, "hipEventCreate");
+    }
+    if ((rc = stage_tasks(p, tasks, ntasks))) {
+        const std::string msg = g_last_error;
+        free_plan(p);
+        return fail(rc, msg);
+    }
+    e = hipMemcpy(p->dev, p->host, p->bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        free_plan(p);
+        return fail_hip(e, "hipMemcpy");
+    }
+    // Capture the persistent launch once; later task lists only change the
+    // device table the kernel reads, so the graph is replayed unchanged.
+    hipStream_t cs = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        free_plan(p);
+        return fail_hip(e, "hipStreamCreate");
+    }
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        rc = launch_plan(p, cs);
+        hipError_t e2 = hipStreamEndCapture(cs, &p->graph);
+        if (rc == FDBB_OK && e2 != hipSuccess) rc = fail_hip(e2, "hipStreamEndCapture");
+    } else {
+        rc = fail_hip(e, "hipStreamBeginCapture");
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc == FDBB_OK) {
+        e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = fail_hip(e, "hipGraphInstantiate");
+    }
+    if (rc) {
+        const std::string msg = g_last_error;
+        free_plan(p);
+        return fail(rc, msg);
+    }
+    *plan = p;
+    return FDBB_OK;
+}
+
+int fdbb_batch_plan_update(fdbb_batch_plan *plan, const fdbb_task *tasks, int ntasks, void *stream)
+{
+    g_last_error.clear();
+    if (!plan) return fail(FDBB_EINVAL, "plan must not be NULL");
+    int rc = stage_tasks(plan, tasks, ntasks);
+    if (rc) return rc;
+    return upload(plan, (hipStream_t)stream);
+}
+
+int fdbb_batch_exec(fdbb_batch_plan *plan, void *stream, int use_graph)
+{
+    g_last_error.clear();
+    if (!plan) return fail(FDBB_EINVAL, "plan must not be NULL");
+    if (plan->tiles == 0) return FDBB_OK;
+    if (use_graph) {
+        hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+        if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
+        return FDBB_OK;
+    }
+    return launch_plan(plan, (hipStream_t)stream);
+}
+
+int fdbb_batch_plan_info(const fdbb_batch_plan *plan, int64_t *points, int64_t *tiles)
+{
+    if (!plan) return fail(FDBB_EINVAL, "plan must not be NULL");
+    if (points) *points = plan->points;
+    if (tiles) *tiles = plan->tiles;
+    return FDBB_OK;
+}
+
+int fdbb_batch_plan_destroy(fdbb_batch_plan *plan)
+{
+    free_plan(plan);
+    return FDBB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,49 @@
+// Host-side glue between the C ABI (fdbb_api.hip) and the kernel
+// translation units.  Each kernel unit returns the address of the template
+// instance for (dim, dtype, points per thread).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "euler_tiles.hpp"
+
+namespace fdbb {
+
+// Device image of one batch task: the operation's arguments plus what the
+// persistent kernel needs to pick the tile function.
+struct TaskDev {
+    Args a;
+    int32_t op;
+    int32_t dim;
+    int32_t dtype;
+    int32_t pad;
+};
+
+// Kernel families (a family covers one or more public ops).
+enum Family : int {
+    kFamCons2Prim = 0,
+    kFamPrim2Cons,
+    kFamEos,
+    kFamFlux,
+    kFamRiemann,
+    kFamCons2Char,
+    kFamChar2Cons,
+    kFamFused,  // fused pass and flux Jacobian (F and R NULL)
+    kFamAdjoint,
+    kNumFamilies
+};
+
+// Single-operation kernels: void k(Args a, int64_t ntiles).
+const void *kernel_pointwise(int family, int dim, int dtype, int ppt);
+const void *kernel_char(int family, int dim, int dtype, int ppt);
+const void *kernel_fused(int dim, int dtype, int ppt);
+const void *kernel_adjoint(int dim, int dtype, int ppt);
+
+// Persistent batch kernel: void k(const TaskDev*, const int64_t* prefix,
+// const int64_t* header).  header = {ntasks, ntiles}; prefix has ntasks + 1
+// entries, prefix[b] = first tile of task b.
+const void *kernel_batch(int ppt);
+
+}  // namespace fdbb

@@ -1,0 +1,39 @@
+// Adjoint kernel: Ubar = sum_d A_d(U)^T Fbar_d (or one direction) without
+// forming A_d.
+#include "fdbb_internal.hpp"
+
+namespace fdbb {
+
+template <int D, typename T, int P>
+__global__ __launch_bounds__(1024) void k_adjoint(Args a, int64_t ntiles)
+{
+    const int64_t tile_pts = (int64_t)blockDim.x * P;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) tile_adjoint<D, T, P>(a, t * tile_pts);
+}
+
+template <int D, typename T>
+static const void *pick_p(int ppt)
+{
+    switch (ppt) {
+    case 1: return (const void *)&k_adjoint<D, T, 1>;
+    case 2: return (const void *)&k_adjoint<D, T, 2>;
+    case 4: return (const void *)&k_adjoint<D, T, 4>;
+    default: return nullptr;
+    }
+}
+
+const void *kernel_adjoint(int dim, int dtype, int ppt)
+{
+    if (dtype == 0) {
+        if (dim == 1) return pick_p<1, double>(ppt);
+        if (dim == 2) return pick_p<2, double>(ppt);
+        if (dim == 3) return pick_p<3, double>(ppt);
+    } else {
+        if (dim == 1) return pick_p<1, float>(ppt);
+        if (dim == 2) return pick_p<2, float>(ppt);
+        if (dim == 3) return pick_p<3, float>(ppt);
+    }
+    return nullptr;
+}
+
+}  // namespace fdbb

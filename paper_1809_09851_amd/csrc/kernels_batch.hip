@@ -1,0 +1,68 @@
+// Persistent batch kernel: a fixed grid of workgroups walks the tiles of
+// many independent tasks of uneven size.  Tiles are dealt round-robin
+// (tile t to workgroup t mod gridDim.x); the owning task of a tile is found
+// by binary search in the tile prefix sums.  Every tile costs about the
+// same, so the static deal balances without a shared counter.
+#include "fdbb_internal.hpp"
+
+namespace fdbb {
+
+template <int D, typename T, int P>
+__device__ __forceinline__ void run_tile(int op, const Args &a, int64_t tile0, unsigned char *smem)
+{
+    switch (op) {
+    case 0: tile_cons2prim<D, T, P>(a, tile0); break;
+    case 1: tile_prim2cons<D, T, P>(a, tile0); break;
+    case 2: tile_eos<D, T, P>(a, tile0); break;
+    case 3: tile_flux<D, T, P>(a, tile0); break;
+    case 4:
+    case 8: tile_fused<D, T, P>(a, tile0, reinterpret_cast<T *>(smem)); break;
+    case 5: tile_riemann<D, T, P>(a, tile0); break;
+    case 6: tile_cons2char<D, T, P>(a, tile0); break;
+    case 7: tile_char2cons<D, T, P>(a, tile0); break;
+    case 9: tile_adjoint<D, T, P>(a, tile0); break;
+    default: break;
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(1024) void k_batch(const TaskDev *__restrict__ tasks,
+                                                const int64_t *__restrict__ prefix,
+                                                const int64_t *__restrict__ header)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int ntasks = (int)header[0];
+    const int64_t ntiles = header[1];
+    const int64_t tile_pts = (int64_t)blockDim.x * P;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int lo = 0, hi = ntasks - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const TaskDev &td = tasks[lo];
+        const int64_t tile0 = (t - prefix[lo]) * tile_pts;
+        if (td.dtype == 0) {
+            if (td.dim == 1) run_tile<1, double, P>(td.op, td.a, tile0, smem);
+            else if (td.dim == 2) run_tile<2, double, P>(td.op, td.a, tile0, smem);
+            else run_tile<3, double, P>(td.op, td.a, tile0, smem);
+        } else {
+            if (td.dim == 1) run_tile<1, float, P>(td.op, td.a, tile0, smem);
+            else if (td.dim == 2) run_tile<2, float, P>(td.op, td.a, tile0, smem);
+            else run_tile<3, float, P>(td.op, td.a, tile0, smem);
+        }
+    }
+}
+
+const void *kernel_batch(int ppt)
+{
+    switch (ppt) {
+    case 1: return (const void *)&k_batch<1>;
+    case 2: return (const void *)&k_batch<2>;
+    case 4: return (const void *)&k_batch<4>;
+    default: return nullptr;
+    }
+}
+
+}  // namespace fdbb

@@ -1,0 +1,43 @@
+// Fused pass kernel: flux tensor, flux Jacobian blocks (staged through LDS)
+// and Riemann invariants of the same state in one pass.  The flux-Jacobian
+// entry point runs this kernel with the flux and invariant outputs NULL.
+#include "fdbb_internal.hpp"
+
+namespace fdbb {
+
+template <int D, typename T, int P>
+__global__ __launch_bounds__(1024) void k_fused(Args a, int64_t ntiles)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    T *lds = reinterpret_cast<T *>(smem);
+    const int64_t tile_pts = (int64_t)blockDim.x * P;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x)
+        tile_fused<D, T, P>(a, t * tile_pts, lds);
+}
+
+template <int D, typename T>
+static const void *pick_p(int ppt)
+{
+    switch (ppt) {
+    case 1: return (const void *)&k_fused<D, T, 1>;
+    case 2: return (const void *)&k_fused<D, T, 2>;
+    case 4: return (const void *)&k_fused<D, T, 4>;
+    default: return nullptr;
+    }
+}
+
+const void *kernel_fused(int dim, int dtype, int ppt)
+{
+    if (dtype == 0) {
+        if (dim == 1) return pick_p<1, double>(ppt);
+        if (dim == 2) return pick_p<2, double>(ppt);
+        if (dim == 3) return pick_p<3, double>(ppt);
+    } else {
+        if (dim == 1) return pick_p<1, float>(ppt);
+        if (dim == 2) return pick_p<2, float>(ppt);
+        if (dim == 3) return pick_p<3, float>(ppt);
+    }
+    return nullptr;
+}
+
+}  // namespace fdbb

@@ -1,0 +1,60 @@
+// Single-operation kernels for the pointwise building blocks: cons2prim,
+// prim2cons, EOS, flux tensor and Riemann invariants.  Each workgroup loops
+// over tiles of blockDim.x * P points (grid-stride when the grid is capped).
+#include "fdbb_internal.hpp"
+
+namespace fdbb {
+
+template <int FAM, int D, typename T, int P>
+__global__ __launch_bounds__(1024) void k_pointwise(Args a, int64_t ntiles)
+{
+    const int64_t tile_pts = (int64_t)blockDim.x * P;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t tile0 = t * tile_pts;
+        if constexpr (FAM == kFamCons2Prim) tile_cons2prim<D, T, P>(a, tile0);
+        else if constexpr (FAM == kFamPrim2Cons) tile_prim2cons<D, T, P>(a, tile0);
+        else if constexpr (FAM == kFamEos) tile_eos<D, T, P>(a, tile0);
+        else if constexpr (FAM == kFamFlux) tile_flux<D, T, P>(a, tile0);
+        else if constexpr (FAM == kFamRiemann) tile_riemann<D, T, P>(a, tile0);
+    }
+}
+
+template <int FAM, int D, typename T>
+static const void *pick_p(int ppt)
+{
+    switch (ppt) {
+    case 1: return (const void *)&k_pointwise<FAM, D, T, 1>;
+    case 2: return (const void *)&k_pointwise<FAM, D, T, 2>;
+    case 4: return (const void *)&k_pointwise<FAM, D, T, 4>;
+    default: return nullptr;
+    }
+}
+
+template <int FAM>
+static const void *pick(int dim, int dtype, int ppt)
+{
+    if (dtype == 0) {
+        if (dim == 1) return pick_p<FAM, 1, double>(ppt);
+        if (dim == 2) return pick_p<FAM, 2, double>(ppt);
+        if (dim == 3) return pick_p<FAM, 3, double>(ppt);
+    } else {
+        if (dim == 1) return pick_p<FAM, 1, float>(ppt);
+        if (dim == 2) return pick_p<FAM, 2, float>(ppt);
+        if (dim == 3) return pick_p<FAM, 3, float>(ppt);
+    }
+    return nullptr;
+}
+
+const void *kernel_pointwise(int family, int dim, int dtype, int ppt)
+{
+    switch (family) {
+    case kFamCons2Prim: return pick<kFamCons2Prim>(dim, dtype, ppt);
+    case kFamPrim2Cons: return pick<kFamPrim2Cons>(dim, dtype, ppt);
+    case kFamEos: return pick<kFamEos>(dim, dtype, ppt);
+    case kFamFlux: return pick<kFamFlux>(dim, dtype, ppt);
+    case kFamRiemann: return pick<kFamRiemann>(dim, dtype, ppt);
+    default: return nullptr;
+    }
+}
+
+}  // namespace fdbb

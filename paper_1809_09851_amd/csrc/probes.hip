@@ -1,0 +1,95 @@
+// Streaming probes (declared in include/fdbb_probe.h): grid-stride loops of
+// 16-byte accesses, 256 threads per workgroup.  grid <= 0 launches 8
+// workgroups per compute unit.
+#include "../../include/fdbb.h"
+#include "../../include/fdbb_probe.h"
+
+#include <hip/hip_runtime.h>
+
+namespace {
+
+using u64x2 = unsigned long long __attribute__((ext_vector_type(2)));
+
+__global__ __launch_bounds__(256) void k_copy(const u64x2 *__restrict__ src, u64x2 *__restrict__ dst,
+                                              int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        __builtin_nontemporal_store(src[i], dst + i);
+}
+
+__global__ __launch_bounds__(256) void k_write(u64x2 *__restrict__ dst, int64_t n, unsigned long long pat)
+{
+    u64x2 v;
+    v.x = pat;
+    v.y = pat;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        __builtin_nontemporal_store(v, dst + i);
+}
+
+__global__ __launch_bounds__(256) void k_read(const u64x2 *__restrict__ src, int64_t n,
+                                              unsigned long long *__restrict__ sink)
+{
+    __shared__ unsigned long long part[256];
+    unsigned long long acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const u64x2 v = src[i];
+        acc ^= v.x ^ v.y;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) part[threadIdx.x] ^= part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sink[blockIdx.x] = part[0];
+}
+
+int grid_for(int grid)
+{
+    if (grid > 0) return grid;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
+    return 8 * cus;
+}
+
+bool aligned(const void *p) { return p && ((uintptr_t)p % 16) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+int fdbb_probe_copy(const void *src, void *dst, int64_t bytes, int grid, void *stream)
+{
+    if (!aligned(src) || !aligned(dst) || bytes < 0 || bytes % 16) return FDBB_EINVAL;
+    if (bytes == 0) return FDBB_OK;
+    const int g = grid_for(grid);
+    if (g <= 0) return FDBB_EHIP;
+    hipLaunchKernelGGL(k_copy, dim3(g), dim3(256), 0, (hipStream_t)stream, (const u64x2 *)src, (u64x2 *)dst,
+                       bytes / 16);
+    return hipGetLastError() == hipSuccess ? FDBB_OK : FDBB_EHIP;
+}
+
+int fdbb_probe_write(void *dst, int64_t bytes, uint64_t pattern, int grid, void *stream)
+{
+    if (!aligned(dst) || bytes < 0 || bytes % 16) return FDBB_EINVAL;
+    if (bytes == 0) return FDBB_OK;
+    const int g = grid_for(grid);
+    if (g <= 0) return FDBB_EHIP;
+    hipLaunchKernelGGL(k_write, dim3(g), dim3(256), 0, (hipStream_t)stream, (u64x2 *)dst, bytes / 16,
+                       (unsigned long long)pattern);
+    return hipGetLastError() == hipSuccess ? FDBB_OK : FDBB_EHIP;
+}
+
+int fdbb_probe_read(const void *src, int64_t bytes, uint64_t *sink, int grid, void *stream)
+{
+    if (!aligned(src) || !sink || bytes < 0 || bytes % 16) return FDBB_EINVAL;
+    if (bytes == 0) return FDBB_OK;
+    const int g = grid_for(grid);
+    if (g <= 0) return FDBB_EHIP;
+    hipLaunchKernelGGL(k_read, dim3(g), dim3(256), 0, (hipStream_t)stream, (const u64x2 *)src, bytes / 16,
+                       (unsigned long long *)sink);
+    return hipGetLastError() == hipSuccess ? FDBB_OK : FDBB_EHIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,131 @@
+"""The C ABI without a GPU: the library loads, exports every symbol that
+include/fdbb.h declares, and rejects bad arguments on the host before any
+HIP call.  No call here reaches a kernel launch."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+from paper_1809_09851_amd import fdbb as F
+
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
+
+
+def declared_symbols():
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names.update(re.findall(r"\b(fdbb_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return F.library()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_symbols()
+    assert len(HEADERS) >= 2
+    assert len(names) >= 23
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_required_entry_points_present():
+    names = declared_symbols()
+    for n in ("fdbb_cons2prim", "fdbb_prim2cons", "fdbb_eos", "fdbb_flux", "fdbb_flux_jacobian",
+              "fdbb_riemann_invariants"):
+        assert n in names
+
+
+def test_status_strings_and_version(lib):
+    assert lib.fdbb_status_string(0) == b"ok"
+    assert lib.fdbb_status_string(F.EALIAS) == b"input and output overlap"
+    assert lib.fdbb_version() >= 100
+
+
+# Fake device addresses: validation rejects these calls before any HIP call.
+A0 = 0x10000000
+B0 = 0x20000000
+
+
+def flux(dim=3, gamma=1.4, dtype=0, U=A0, ldU=128, Fp=B0, ldF=128, n=100):
+    return F.library().fdbb_flux(dim, gamma, dtype, U, ldU, Fp, ldF, n, None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(dim=0), F.EINVAL), (dict(dim=4), F.EINVAL),
+    (dict(gamma=1.0), F.EINVAL), (dict(gamma=0.5), F.EINVAL),
+    (dict(gamma=float("nan")), F.EINVAL), (dict(gamma=float("inf")), F.EINVAL),
+    (dict(dtype=2), F.EINVAL), (dict(n=-1), F.EINVAL),
+    (dict(U=0), F.EINVAL), (dict(Fp=0), F.EINVAL),
+    (dict(ldU=99), F.EINVAL), (dict(ldF=50), F.EINVAL),
+    (dict(U=A0 + 4), F.EALIGN), (dict(Fp=B0 + 2, dtype=1), F.EALIGN),
+    (dict(Fp=A0 + 8 * 64), F.EALIAS),             # F starts inside U
+    (dict(Fp=A0, ldF=128), F.EALIAS),             # same base as U
+])
+def test_flux_rejects(kw, status):
+    assert flux(**kw) == status
+    assert F.library().fdbb_last_error() != b""
+
+
+def test_zero_points_is_a_noop():
+    # n == 0 returns before any HIP call, even with NULL pointers.
+    assert flux(n=0, U=0, Fp=0) == F.OK
+    lib = F.library()
+    assert lib.fdbb_cons2prim(2, 1.4, 0, None, 0, None, 0, 0, None) == F.OK
+
+
+def test_inplace_rules():
+    lib = F.library()
+    # partial overlap of a K -> K transform: rejected
+    assert lib.fdbb_cons2prim(2, 1.4, 0, A0, 128, A0 + 8, 128, 100, None) == F.EALIAS
+    # same base, different ld: rejected
+    assert lib.fdbb_prim2cons(2, 1.4, 0, A0, 128, A0, 256, 100, None) == F.EALIAS
+    # exact in place is not allowed for ops whose output is not the state
+    assert lib.fdbb_riemann_invariants(1, 1.4, 0, A0, 128, A0, 128, 100, None) == F.EALIAS
+
+
+def test_eos_and_fused_nullable_outputs():
+    lib = F.library()
+    assert lib.fdbb_eos(3, 1.4, 0, A0, 128, None, None, 100, None) == F.EINVAL
+    assert lib.fdbb_eos(3, 1.4, 0, A0, 128, A0 + 8, None, 100, None) == F.EALIAS
+    assert lib.fdbb_euler_fused(3, 1.4, 0, A0, 128, None, 0, None, 0, None, 0, 100, None) == F.EINVAL
+    # F of D = 2 spans (7 * 128 + 100) doubles; A starting inside it overlaps
+    assert lib.fdbb_euler_fused(2, 1.4, 0, A0, 128, B0, 128, B0 + 8 * 64, 128, None, 0, 100,
+                                None) == F.EALIAS
+
+
+def test_direction_checks():
+    lib = F.library()
+    assert lib.fdbb_cons2char(2, 2, 1.4, 0, A0, 128, B0, 128, 100, None) == F.EINVAL
+    assert lib.fdbb_char2cons(1, -1, 1.4, 0, A0, 128, B0, 128, 100, None) == F.EINVAL
+    assert lib.fdbb_flux_adjoint(3, 3, 1.4, 0, A0, 128, B0, 128, A0 + 10**7, 128, 100, None) == F.EINVAL
+    assert lib.fdbb_flux_adjoint(3, -2, 1.4, 0, A0, 128, B0, 128, A0 + 10**7, 128, 100, None) == F.EINVAL
+
+
+def test_launch_config_table():
+    assert F.library().fdbb_set_launch_config(3, 3, 0, 100, 1, 0) == F.EINVAL   # not a multiple of 64
+    assert F.library().fdbb_set_launch_config(3, 3, 0, 256, 3, 0) == F.EINVAL   # ppt
+    assert F.library().fdbb_set_launch_config(3, 3, 0, 2048, 1, 0) == F.EINVAL
+    assert F.library().fdbb_set_launch_config(99, 3, 0, 256, 1, 0) == F.EINVAL
+    old = F.fdbb_get_launch_config("flux", 3, 0)
+    F.fdbb_set_launch_config("flux", 3, 0, 512, 4, 1000)
+    assert F.fdbb_get_launch_config("flux", 3, 0) == (512, 4, 1000)
+    F.fdbb_set_launch_config("flux", 3, 0, *old)
+    assert F.fdbb_get_launch_config("flux", 3, 0) == old
+
+
+def test_batch_plan_rejects_bad_tasks():
+    lib = F.library()
+    plan = ctypes.c_void_p()
+    t = (F.Task * 1)()
+    t[0].op, t[0].dim, t[0].dtype, t[0].gamma, t[0].n = 3, 4, 0, 1.4, 10
+    assert lib.fdbb_batch_plan_create(t, 1, 1, 256, 1, 0, ctypes.byref(plan)) == F.EINVAL
+    assert lib.fdbb_batch_plan_create(t, 1, 0, 256, 1, 0, ctypes.byref(plan)) == F.EINVAL
+    assert lib.fdbb_batch_plan_create(t, 1, 1, 100, 1, 0, ctypes.byref(plan)) == F.EINVAL
+    assert not plan.value

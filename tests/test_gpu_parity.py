@@ -1,0 +1,276 @@
+"""HIP kernels against the CPU oracle, element by element, through the C ABI.
+
+Sizes span several tiles (256 threads x up to 4 points) and ragged tails.
+Tolerances and the error metric are those of tests/metrics.py.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_common import DTYPES, GAMMA, host, prim_states, require_gpu, states
+from metrics import (TOL, blocks_error, char_groups, flux_groups, group_error, riemann_groups,
+                     state_groups)
+from paper_1809_09851_amd import fdbb as F
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (1, 2, 3)
+DTS = ("f64", "f32")
+SIZES = (1, 63, 64, 65, 1000, 5003)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _seed(dim, n, dt, k=0):
+    return 1000 * dim + (n % 997) + (0 if dt == "f64" else 500) + 7 * k
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("dim", DIMS)
+@pytest.mark.parametrize("n", SIZES)
+def test_cons2prim(dim, dt, n):
+    Uo, Ug = states(dim, n, _seed(dim, n, dt), dt)
+    V = F.cons2prim(Ug, GAMMA)
+    assert group_error(host(V), oracle.cons2prim(dim, GAMMA, Uo), state_groups(dim)) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("dim", DIMS)
+@pytest.mark.parametrize("n", SIZES)
+def test_prim2cons(dim, dt, n):
+    Vo, Vg = prim_states(dim, n, _seed(dim, n, dt, 1), dt)
+    U = F.prim2cons(Vg, GAMMA)
+    assert group_error(host(U), oracle.prim2cons(dim, GAMMA, Vo), state_groups(dim)) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("dim", DIMS)
+@pytest.mark.parametrize("n", SIZES)
+def test_eos(dim, dt, n):
+    Uo, Ug = states(dim, n, _seed(dim, n, dt, 2), dt)
+    p, c = F.eos(Ug, GAMMA)
+    po, co = oracle.eos(dim, GAMMA, Uo)
+    assert group_error(host(p)[None], po[None], [[0]]) <= TOL[dt]
+    assert group_error(host(c)[None], co[None], [[0]]) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("dim", DIMS)
+def test_eos_single_output(dim, dt):
+    n = 777
+    Uo, Ug = states(dim, n, 3, dt)
+    po, co = oracle.eos(dim, GAMMA, Uo)
+    c = torch.empty(n, dtype=DTYPES[dt], device="cuda")
+    F.fdbb_eos(dim, GAMMA, Ug, None, c)
+    assert group_error(host(c)[None], co[None], [[0]]) <= TOL[dt]
+    p = torch.empty(n, dtype=DTYPES[dt], device="cuda")
+    F.fdbb_eos(dim, GAMMA, Ug, p, None)
+    assert group_error(host(p)[None], po[None], [[0]]) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("dim", DIMS)
+@pytest.mark.parametrize("n", SIZES)
+def test_flux(dim, dt, n):
+    Uo, Ug = states(dim, n, _seed(dim, n, dt, 3), dt)
+    Fg = F.flux(Ug, GAMMA)
+    assert group_error(host(Fg), oracle.flux(dim, GAMMA, Uo), flux_groups(dim)) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("dim", DIMS)
+@pytest.mark.parametrize("n", SIZES)
+def test_flux_jacobian(dim, dt, n):
+    Uo, Ug = states(dim, n, _seed(dim, n, dt, 4), dt)
+    A = F.flux_jacobian(Ug, GAMMA)
+    assert blocks_error(host(A), oracle.flux_jacobian(dim, GAMMA, Uo)) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("dim", DIMS)
+@pytest.mark.parametrize("n", SIZES)
+def test_riemann_invariants(dim, dt, n):
+    Uo, Ug = states(dim, n, _seed(dim, n, dt, 5), dt)
+    R = F.riemann_invariants(Ug, GAMMA)
+    assert group_error(host(R), oracle.riemann_invariants(dim, GAMMA, Uo), riemann_groups(dim)) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("dim", DIMS)
+@pytest.mark.parametrize("n", (1, 65, 5003))
+def test_characteristic_transforms(dim, dt, n):
+    Uo, Ug = states(dim, n, _seed(dim, n, dt, 6), dt)
+    for d in range(dim):
+        W = F.cons2char(Ug, d, GAMMA)
+        Wo = oracle.cons2char(dim, d, GAMMA, Uo)
+        assert group_error(host(W), Wo, char_groups(dim)) <= TOL[dt]
+        # inverse, on the exact W the GPU holds
+        Wh = host(W)
+        U2 = F.char2cons(W, d, GAMMA)
+        tol = 1e-11 if dt == "f64" else 1e-5
+        assert group_error(host(U2), oracle.char2cons(dim, d, GAMMA, Wh), state_groups(dim)) <= tol
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("dim", DIMS)
+@pytest.mark.parametrize("n", SIZES)
+def test_fused(dim, dt, n):
+    Uo, Ug = states(dim, n, _seed(dim, n, dt, 7), dt)
+    Fg, A, R = F.euler_fused(Ug, GAMMA)
+    Fo, Ao, Ro = oracle.fused(dim, GAMMA, Uo)
+    assert group_error(host(Fg), Fo, flux_groups(dim)) <= TOL[dt]
+    assert blocks_error(host(A), Ao) <= TOL[dt]
+    assert group_error(host(R), Ro, riemann_groups(dim)) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("dim", DIMS)
+def test_fused_equals_single_ops(dim, dt):
+    n = 4099
+    _, Ug = states(dim, n, 11, dt)
+    Fg, A, R = F.euler_fused(Ug, GAMMA)
+    # Same formulas in separate kernels: equal up to the compiler's choice of
+    # contractions, far inside the oracle tolerance.
+    tol = 1e-14 if dt == "f64" else 1.2e-7
+    assert group_error(host(Fg), host(F.flux(Ug, GAMMA)), flux_groups(dim)) <= tol
+    assert torch.equal(A, F.flux_jacobian(Ug, GAMMA))
+    assert group_error(host(R), host(F.riemann_invariants(Ug, GAMMA)), riemann_groups(dim)) <= tol
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("dim", DIMS)
+def test_fused_partial_outputs(dim, dt):
+    n = 3001
+    Uo, Ug = states(dim, n, 12, dt)
+    Fo, Ao, Ro = oracle.fused(dim, GAMMA, Uo)
+    for want in ((True, False, False), (False, True, False), (False, False, True), (True, False, True)):
+        Fg, A, R = F.euler_fused(Ug, GAMMA, *want)
+        if Fg is not None:
+            assert group_error(host(Fg), Fo, flux_groups(dim)) <= TOL[dt]
+        if A is not None:
+            assert blocks_error(host(A), Ao) <= TOL[dt]
+        if R is not None:
+            assert group_error(host(R), Ro, riemann_groups(dim)) <= TOL[dt]
+
+
+def _adjoint_scale(dim, Uo, Fb, direction):
+    """Per-point |sum_d |A_d|^T |Fbar_d| |_inf from the oracle's Jacobians."""
+    A = np.abs(oracle.flux_jacobian(dim, GAMMA, Uo))
+    K = dim + 2
+    s = np.zeros((K, Uo.shape[1]))
+    for d in range(dim):
+        if direction >= 0 and d != direction:
+            continue
+        fb = Fb if direction >= 0 else np.array([Fb[r * dim + d] for r in range(K)])
+        s += np.einsum("nrc,rn->cn", A[d], np.abs(fb))
+    return s.max(axis=0)
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("dim", DIMS)
+@pytest.mark.parametrize("n", SIZES)
+def test_adjoint(dim, dt, n):
+    from paper_1809_09851_amd import inputs
+    Uo, Ug = states(dim, n, _seed(dim, n, dt, 8), dt)
+    K = dim + 2
+    for direction in [-1] + list(range(dim)):
+        fields = K * dim if direction < 0 else K
+        Fb = inputs.cotangent(dim, n, _seed(dim, n, dt, 9) + direction, fields)
+        Fb = Fb.astype(np.float32 if dt == "f32" else np.float64).astype(np.float64)
+        Fbg = F.to_fields(torch.from_numpy(Fb).to(DTYPES[dt]).cuda())
+        Ub = F.flux_adjoint(Ug, Fbg, GAMMA, direction)
+        ref = oracle.flux_adjoint(dim, direction, GAMMA, Uo, Fb)
+        err = group_error(host(Ub), ref, [list(range(K))], denom=_adjoint_scale(dim, Uo, Fb, direction))
+        assert err <= TOL[dt], (direction, err)
+
+
+# ------------------------------------------------------------ edge cases
+
+def test_zero_points_leave_outputs_untouched():
+    _, Ug = states(3, 10, 1)
+    out = torch.full((15, 64), 7.0, dtype=torch.float64, device="cuda")
+    F.fdbb_flux(3, GAMMA, Ug, out[:, :10], n=0)
+    assert torch.all(out == 7.0)
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("dim", DIMS)
+def test_unpadded_and_offset_views(dim, dt):
+    """Rows of odd length and views starting at an odd element take the
+    scalar path; results must not change."""
+    n = 1001
+    Uo, Ug = states(dim, n + 1, 21, dt)
+    K = dim + 2
+    tight = torch.from_numpy(Uo.astype(np.float32 if dt == "f32" else np.float64)).cuda().contiguous()
+    assert tight.stride(0) == n + 1
+    for U_view, Uref in ((tight, Uo), (tight[:, 1:], Uo[:, 1:])):
+        Fo = oracle.flux(dim, GAMMA, Uref)
+        Fg = F.flux(U_view, GAMMA)
+        assert group_error(host(Fg), Fo, flux_groups(dim)) <= TOL[dt]
+        A = F.flux_jacobian(U_view, GAMMA)
+        assert blocks_error(host(A), oracle.flux_jacobian(dim, GAMMA, Uref)) <= TOL[dt]
+        # outputs with odd rows too
+        Fo2 = torch.empty((K * dim, U_view.shape[1]), dtype=DTYPES[dt], device="cuda")
+        F.fdbb_flux(dim, GAMMA, U_view, Fo2)
+        assert group_error(host(Fo2), Fo, flux_groups(dim)) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("dim", DIMS)
+def test_in_place_transforms(dim, dt):
+    n = 2049
+    Uo, Ug = states(dim, n, 31, dt)
+    rho_before = Ug[0].clone()
+    F.fdbb_cons2prim(dim, GAMMA, Ug, Ug)
+    assert torch.equal(Ug[0], rho_before)
+    assert group_error(host(Ug), oracle.cons2prim(dim, GAMMA, Uo), state_groups(dim)) <= TOL[dt]
+    Vh = host(Ug)
+    F.fdbb_prim2cons(dim, GAMMA, Ug, Ug)
+    assert torch.equal(Ug[0], rho_before)
+    assert group_error(host(Ug), oracle.prim2cons(dim, GAMMA, Vh), state_groups(dim)) <= TOL[dt]
+    Uh = host(Ug)
+    F.fdbb_cons2char(dim, dim - 1, GAMMA, Ug, Ug)
+    assert group_error(host(Ug), oracle.cons2char(dim, dim - 1, GAMMA, Uh), char_groups(dim)) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dim", DIMS)
+def test_near_vacuum_states(dim):
+    n = 20000
+    Uo, Ug = states(dim, n, 41, "f64", vacuum=0.05)
+    Fg, A, R = F.euler_fused(Ug, GAMMA)
+    Fo, Ao, Ro = oracle.fused(dim, GAMMA, Uo)
+    assert group_error(host(Fg), Fo, flux_groups(dim)) <= TOL["f64"]
+    assert blocks_error(host(A), Ao) <= TOL["f64"]
+    assert group_error(host(R), Ro, riemann_groups(dim)) <= TOL["f64"]
+
+
+@pytest.mark.parametrize("dim", DIMS)
+def test_non_admissible_states_propagate_like_the_oracle(dim):
+    """rho < 0 or p < 0 is not an error: NaN/Inf land where the oracle's do."""
+    n = 512
+    Uo, _ = states(dim, n, 51)
+    Uo[0, ::7] *= -1.0                       # negative density
+    Uo[dim + 1, 3::11] *= -1.0               # negative energy -> negative p
+    Uo[0, 5] = 0.0                           # zero density
+    Ug = F.to_fields(torch.from_numpy(Uo).cuda())
+    p, c = F.eos(Ug, GAMMA)
+    po, co = oracle.eos(dim, GAMMA, Uo)
+    assert group_error(host(p)[None], po[None], [[0]]) <= TOL["f64"]
+    assert group_error(host(c)[None], co[None], [[0]]) <= TOL["f64"]
+    R = F.riemann_invariants(Ug, GAMMA)
+    assert np.isnan(host(R)).any()
+    assert group_error(host(R), oracle.riemann_invariants(dim, GAMMA, Uo), riemann_groups(dim)) <= TOL["f64"]
+
+
+def test_other_gammas():
+    for g in (5.0 / 3.0, 1.1, 1.3):
+        Uo, Ug = states(3, 3000, 61)
+        Fg, A, R = F.euler_fused(Ug, g)
+        Fo, Ao, Ro = oracle.fused(3, g, Uo)
+        assert group_error(host(Fg), Fo, flux_groups(3)) <= TOL["f64"]
+        assert blocks_error(host(A), Ao) <= TOL["f64"]
+        assert group_error(host(R), Ro, riemann_groups(3)) <= TOL["f64"]
