@@ -1,0 +1,189 @@
+"""Persistent batch plans: many uneven blocks in one launch, replayed from a
+HIP graph, against single launches and the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_common import GAMMA, host, require_gpu, states
+from metrics import TOL, blocks_error, flux_groups, group_error, riemann_groups, state_groups
+from paper_1809_09851_amd import batch as B
+from paper_1809_09851_amd import fdbb as F
+from paper_1809_09851_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _blocks(nb, seed, dt="f64", lo=1, hi=20000):
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(lo, hi, nb)
+    out = []
+    for b, n in enumerate(sizes):
+        Uo, Ug = states(3, int(n), seed * 1000 + b, dt, vacuum=0.05)
+        out.append((Uo, Ug))
+    return out
+
+
+@pytest.mark.parametrize("dt", ("f64", "f32"))
+@pytest.mark.parametrize("ppt", (1, 2))
+def test_fused_batch_matches_oracle_and_single_launches(dt, ppt):
+    blocks = _blocks(37, 3 + ppt, dt)
+    outs, tasks = [], []
+    for Uo, Ug in blocks:
+        n = Ug.shape[1]
+        o = (F.empty_fields(15, n, Ug.dtype), F.empty_blocks(3, n, Ug.dtype), F.empty_fields(7, n, Ug.dtype))
+        outs.append(o)
+        tasks.append(B.fused_task(Ug, *o, gamma=GAMMA))
+    plan = B.Plan(tasks, block=256, ppt=ppt)
+    pts, tiles = plan.info()
+    assert pts == sum(Ug.shape[1] for _, Ug in blocks)
+    plan.run(graph=True)
+    torch.cuda.synchronize()
+    for (Uo, Ug), (Fg, A, R) in zip(blocks, outs):
+        Fo, Ao, Ro = oracle.fused(3, GAMMA, Uo)
+        assert group_error(host(Fg), Fo, flux_groups(3)) <= TOL[dt]
+        assert blocks_error(host(A), Ao) <= TOL[dt]
+        assert group_error(host(R), Ro, riemann_groups(3)) <= TOL[dt]
+        F1, A1, R1 = F.euler_fused(Ug, GAMMA)
+        assert torch.equal(A1, A)
+        tol = 1e-14 if dt == "f64" else 1.2e-7
+        assert group_error(host(F1), host(Fg), flux_groups(3)) <= tol
+        assert group_error(host(R1), host(R), riemann_groups(3)) <= tol
+    plan.close()
+
+
+def test_graph_replays_with_eager_work_between():
+    blocks = _blocks(12, 9)
+    outs, tasks = [], []
+    for Uo, Ug in blocks:
+        n = Ug.shape[1]
+        o = (F.empty_fields(15, n), F.empty_blocks(3, n), F.empty_fields(7, n))
+        outs.append(o)
+        tasks.append(B.fused_task(Ug, *o, gamma=GAMMA))
+    plan = B.Plan(tasks, block=256, ppt=1)
+    plan.run(graph=False)
+    torch.cuda.synchronize()
+    ref = [tuple(t.clone() for t in o) for o in outs]
+    for rep in range(4):
+        for o in outs:
+            for t in o:
+                t.zero_()
+        _ = torch.randn(1 << 20, device="cuda").sum()  # unrelated eager work
+        torch.cuda.synchronize()
+        plan.run(graph=True)
+        torch.cuda.synchronize()
+        for o, r in zip(outs, ref):
+            for t, tr in zip(o, r):
+                assert torch.equal(t, tr), f"replay {rep} differs"
+    plan.close()
+
+
+def test_update_changes_tasks_without_recapture():
+    blocks = _blocks(8, 11)
+    outs, tasks = [], []
+    for Uo, Ug in blocks:
+        n = Ug.shape[1]
+        o = (F.empty_fields(15, n), F.empty_blocks(3, n), F.empty_fields(7, n))
+        outs.append(o)
+        tasks.append(B.fused_task(Ug, *o, gamma=GAMMA))
+    plan = B.Plan(tasks, capacity=16, block=256, ppt=1)
+    plan.run()
+    # second, smaller list with other states and a different gamma
+    blocks2 = _blocks(5, 12)
+    outs2, tasks2 = [], []
+    for Uo, Ug in blocks2:
+        n = Ug.shape[1]
+        o = (F.empty_fields(15, n), F.empty_blocks(3, n), F.empty_fields(7, n))
+        outs2.append(o)
+        tasks2.append(B.fused_task(Ug, *o, gamma=5.0 / 3.0))
+    plan.update(tasks2)
+    plan.run()
+    torch.cuda.synchronize()
+    for (Uo, Ug), (Fg, A, R) in zip(blocks2, outs2):
+        Fo, Ao, Ro = oracle.fused(3, 5.0 / 3.0, Uo)
+        assert group_error(host(Fg), Fo, flux_groups(3)) <= TOL["f64"]
+        assert blocks_error(host(A), Ao) <= TOL["f64"]
+    assert plan.info()[0] == sum(Ug.shape[1] for _, Ug in blocks2)
+    with pytest.raises(F.FdbbError):
+        plan.update(tasks2 * 4)  # over capacity
+    plan.close()
+
+
+def _adjoint_denominator(dim, Uo, fb):
+    A = np.abs(oracle.flux_jacobian(dim, GAMMA, Uo))
+    K = dim + 2
+    den = np.zeros((K, Uo.shape[1]))
+    for d in range(dim):
+        den += np.einsum("nrc,rn->cn", A[d], np.abs(np.array([fb[r * dim + d] for r in range(K)])))
+    return den.max(axis=0)
+
+
+def test_mixed_ops_dims_dtypes_in_one_launch():
+    """Serving-style batch: different ops, dims and storage types per task."""
+    rng = np.random.default_rng(21)
+    jobs = []
+    for k in range(30):
+        op = ("cons2prim", "flux", "flux_jacobian", "adjoint", "riemann_invariants")[k % 5]
+        dim = int(rng.integers(1, 4))
+        dt = ("f64", "f32")[k % 2]
+        n = int(rng.integers(1, 9000))
+        Uo, Ug = states(dim, n, 500 + k, dt)
+        K = dim + 2
+        job = {"op": op, "dim": dim, "dt": dt, "Uo": Uo}
+        if op == "cons2prim":
+            job["out"] = F.empty_fields(K, n, Ug.dtype)
+            job["task"] = B.cons2prim_task(Ug, job["out"], GAMMA)
+            job["ref"] = oracle.cons2prim(dim, GAMMA, Uo)
+            job["groups"] = state_groups(dim)
+        elif op == "flux":
+            job["out"] = F.empty_fields(K * dim, n, Ug.dtype)
+            job["task"] = B.flux_task(Ug, job["out"], GAMMA)
+            job["ref"] = oracle.flux(dim, GAMMA, Uo)
+            job["groups"] = flux_groups(dim)
+        elif op == "flux_jacobian":
+            job["out"] = F.empty_blocks(dim, n, Ug.dtype)
+            job["task"] = B.jacobian_task(Ug, job["out"], GAMMA)
+            job["ref"] = oracle.flux_jacobian(dim, GAMMA, Uo)
+        elif op == "riemann_invariants":
+            job["out"] = F.empty_fields(2 * dim + 1, n, Ug.dtype)
+            job["task"] = B.riemann_task(Ug, job["out"], GAMMA)
+            job["ref"] = oracle.riemann_invariants(dim, GAMMA, Uo)
+            job["groups"] = riemann_groups(dim)
+        else:
+            fb = inputs.cotangent(dim, n, 900 + k).astype(np.float32 if dt == "f32" else np.float64)
+            job["fbg"] = F.to_fields(torch.from_numpy(fb).cuda())
+            job["out"] = F.empty_fields(K, n, Ug.dtype)
+            job["task"] = B.adjoint_task(Ug, job["fbg"], job["out"], GAMMA)
+            fb = fb.astype(np.float64)
+            job["ref"] = oracle.flux_adjoint(dim, -1, GAMMA, Uo, fb)
+            job["den"] = _adjoint_denominator(dim, Uo, fb)
+        job["Ug"] = Ug
+        jobs.append(job)
+    plan = B.Plan([j["task"] for j in jobs], block=256, ppt=1)
+    plan.run()
+    torch.cuda.synchronize()
+    for j in jobs:
+        tol = TOL[j["dt"]]
+        if j["op"] == "flux_jacobian":
+            assert blocks_error(host(j["out"]), j["ref"]) <= tol
+        elif j["op"] == "adjoint":
+            K = j["dim"] + 2
+            assert group_error(host(j["out"]), j["ref"], [list(range(K))], denom=j["den"]) <= tol
+        else:
+            assert group_error(host(j["out"]), j["ref"], j["groups"]) <= tol
+    plan.close()
+
+
+def test_overlapping_tasks_are_rejected():
+    _, Ug = states(3, 1000, 1)
+    out = F.empty_fields(15, 1000)
+    t1 = B.flux_task(Ug, out, GAMMA)
+    t2 = B.flux_task(Ug, out, GAMMA)
+    with pytest.raises(F.FdbbError) as e:
+        B.Plan([t1, t2])
+    assert e.value.status == F.EALIAS

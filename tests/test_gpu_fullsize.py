@@ -1,0 +1,126 @@
+"""The measured workloads at full size, in the launch configuration the
+benchmark times: sampled outputs against the oracle point by point, and
+properties that hold at any size."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_common import GAMMA, NP, host, require_gpu
+from metrics import TOL, blocks_error, flux_groups, group_error, riemann_groups, state_groups
+from paper_1809_09851_amd import fdbb as F
+from paper_1809_09851_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _sample(n, seed, k=1 << 15):
+    rng = np.random.default_rng(seed)
+    idx = np.unique(np.concatenate([np.arange(min(n, 2048)), np.arange(max(0, n - 2048), n),
+                                    rng.integers(0, n, k)]))
+    return idx
+
+
+@pytest.mark.parametrize("dt", ("f64", "f32"))
+def test_fused_3d_2p24_sampled(dt):
+    n = 1 << 24
+    V = inputs.gaussian(3, n, 1)
+    U = oracle.prim2cons(3, GAMMA, V).astype(NP[dt])
+    del V
+    Ug = F.to_fields(torch.from_numpy(U).cuda())
+    Fg, A, R = F.euler_fused(Ug, GAMMA)
+    torch.cuda.synchronize()
+    idx = _sample(n, 5)
+    it = torch.from_numpy(idx).cuda()
+    Us = U[:, idx].astype(np.float64)
+    Fo, Ao, Ro = oracle.fused(3, GAMMA, Us)
+    assert group_error(host(Fg[:, it]), Fo, flux_groups(3)) <= TOL[dt]
+    assert blocks_error(host(A[:, it]), Ao) <= TOL[dt]
+    assert group_error(host(R[:, it]), Ro, riemann_groups(3)) <= TOL[dt]
+    # at any size: homogeneity A_d U = F_d on every point, on the GPU
+    Ut = Ug.to(torch.float64)
+    for d in range(3):
+        AU = torch.einsum("nrc,cn->rn", A[d].to(torch.float64), Ut)
+        Fd = torch.stack([Fg[r * 3 + d] for r in range(5)]).to(torch.float64)
+        den = Fd.abs().amax(dim=0).clamp_min(1e-300)
+        err = ((AU - Fd).abs().amax(dim=0) / den).max().item()
+        assert err <= (1e-13 if dt == "f64" else 2e-6)
+    del Ug, Fg, A, R
+    torch.cuda.empty_cache()
+
+
+def test_ops_1d_2p20_full():
+    n = 1 << 20
+    V = inputs.uniform_1d(n, 0)
+    U = oracle.prim2cons(1, GAMMA, V)
+    Ug = F.to_fields(torch.from_numpy(U).cuda())
+    assert group_error(host(F.cons2prim(Ug, GAMMA)), oracle.cons2prim(1, GAMMA, U), state_groups(1)) <= TOL["f64"]
+    p, c = F.eos(Ug, GAMMA)
+    po, co = oracle.eos(1, GAMMA, U)
+    assert group_error(host(p)[None], po[None], [[0]]) <= TOL["f64"]
+    assert group_error(host(c)[None], co[None], [[0]]) <= TOL["f64"]
+    assert group_error(host(F.flux(Ug, GAMMA)), oracle.flux(1, GAMMA, U), flux_groups(1)) <= TOL["f64"]
+
+
+@pytest.mark.parametrize("dim", (2, 3))
+def test_adjoint_2p22_against_jacobian_transpose(dim):
+    n = 1 << 22
+    K = dim + 2
+    V = inputs.gaussian(dim, n, 3)
+    U = oracle.prim2cons(dim, GAMMA, V)
+    Fb = inputs.cotangent(dim, n, 3)
+    Ug = F.to_fields(torch.from_numpy(U).cuda())
+    Fbg = F.to_fields(torch.from_numpy(Fb).cuda())
+    Ub = F.flux_adjoint(Ug, Fbg, GAMMA)
+    A = F.flux_jacobian(Ug, GAMMA)
+    # sum_d A_d^T Fbar_d from the Jacobian kernel, every point
+    ref = torch.zeros((n, K, 1), dtype=torch.float64, device="cuda")
+    scale = torch.zeros((n, K, 1), dtype=torch.float64, device="cuda")
+    for d in range(dim):
+        fbd = torch.stack([Fbg[r * dim + d] for r in range(K)]).t().contiguous().unsqueeze(-1)
+        At = A[d].transpose(1, 2).contiguous()
+        ref += torch.matmul(At, fbd)
+        scale += torch.matmul(At.abs(), fbd.abs())
+    ref = ref.squeeze(-1).t()
+    den = scale.squeeze(-1).amax(dim=1)
+    err = ((Ub - ref).abs().amax(dim=0) / den).max().item()
+    assert err <= 1e-13
+    # and the oracle on a sample
+    idx = _sample(n, 7, 1 << 13)
+    it = torch.from_numpy(idx).cuda()
+    ro = oracle.flux_adjoint(dim, -1, GAMMA, U[:, idx], Fb[:, idx])
+    Ao = np.abs(oracle.flux_jacobian(dim, GAMMA, U[:, idx]))
+    d0 = np.zeros((K, idx.size))
+    for d in range(dim):
+        d0 += np.einsum("nrc,rn->cn", Ao[d], np.abs(np.array([Fb[r * dim + d, idx] for r in range(K)])))
+    assert group_error(host(Ub[:, it]), ro, [list(range(K))], denom=d0.max(axis=0)) <= TOL["f64"]
+
+
+@pytest.mark.parametrize("dim", (2, 3))
+def test_adjoint_central_differences(dim):
+    """Directional check of the adjoint against central differences of the
+    GPU flux, h = 1e-6 on each conserved component, N = 4096."""
+    n = 4096
+    K = dim + 2
+    V = inputs.gaussian(dim, n, 3)
+    U = oracle.prim2cons(dim, GAMMA, V)
+    w = inputs.cotangent(dim, n, 4)
+    Ug = F.to_fields(torch.from_numpy(U).cuda())
+    wg = torch.from_numpy(w).cuda()
+    Ub = host(F.flux_adjoint(Ug, F.to_fields(wg), GAMMA))
+    h = 1e-6
+    for k in range(K):
+        Up = U.copy()
+        Um = U.copy()
+        Up[k] += h
+        Um[k] -= h
+        Lp = (wg * F.flux(F.to_fields(torch.from_numpy(Up).cuda()), GAMMA)).sum(dim=0)
+        Lm = (wg * F.flux(F.to_fields(torch.from_numpy(Um).cuda()), GAMMA)).sum(dim=0)
+        fd = host((Lp - Lm) / (2 * h))
+        den = np.maximum(np.abs(Ub).max(axis=0), 1.0)
+        assert np.max(np.abs(fd - Ub[k]) / den) <= 1e-6
