@@ -255,6 +255,8 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=1 << 24)
     ap.add_argument("--extras", action="store_true", help="also time the other building blocks")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--probe-copy", action="store_true",
+                    help="also run the 1 GiB copy probe 3 times (hardware byte-counter calibration)")
     args = ap.parse_args(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: every building block is pointwise and one GPU's "
@@ -308,6 +310,13 @@ def main(argv=None):
         ex["adjoint_f64_2p22"] = bench_adjoint(args.steps, args.warmup)
         ex["hbm_probes_gbs"] = bench_probes(max(10, args.steps // 5), 3)
         line["extras"] = ex
+    if args.probe_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            F.probe_copy(a, b)
+        torch.cuda.synchronize()
+        del a, b
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
