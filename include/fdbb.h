@@ -154,11 +154,15 @@ int fdbb_flux_adjoint(int dim, int dir, double gamma, int dtype, const void *U, 
 /* ---------------------------------------------------------------- tuning
  * Launch configuration per (op, dim, dtype): `block` threads per workgroup
  * (64..1024, a multiple of 64), `ppt` consecutive points per thread
- * (1, 2 or 4) and `grid_cap` the largest grid (0 = one tile per workgroup;
- * otherwise workgroups loop over tiles).  Returns FDBB_EINVAL for values
- * outside these sets.  The table is process-wide. */
-int fdbb_set_launch_config(int op, int dim, int dtype, int block, int ppt, int grid_cap);
-int fdbb_get_launch_config(int op, int dim, int dtype, int *block, int *ppt, int *grid_cap);
+ * (1, 2 or 4), `grid_cap` the largest grid (0 = one tile per workgroup;
+ * otherwise workgroups loop over tiles) and `nontemporal` (1: outputs are
+ * written with non-temporal stores, 0: regular stores).  Returns
+ * FDBB_EINVAL for values outside these sets.  The table is process-wide and
+ * safe to update while other threads launch. */
+int fdbb_set_launch_config(int op, int dim, int dtype, int block, int ppt, int grid_cap,
+                           int nontemporal);
+int fdbb_get_launch_config(int op, int dim, int dtype, int *block, int *ppt, int *grid_cap,
+                           int *nontemporal);
 
 /* ---------------------------------------------------------------- batches
  * Many independent blocks of uneven size in one persistent launch.  A task
@@ -192,10 +196,11 @@ typedef struct fdbb_batch_plan fdbb_batch_plan;
  * into it.  Each task is validated as its single-call entry point would be.
  * The plan owns a device copy of the task table, the tile prefix sums and a
  * HIP graph holding one persistent kernel with `grid` workgroups of `block`
- * threads (grid 0 picks one sized to the device), `ppt` points per thread.
- * Tasks that overlap one another's outputs are rejected (FDBB_EALIAS). */
+ * threads (grid 0 picks one sized to the device), `ppt` points per thread
+ * and non-temporal (1) or regular (0) output stores.  Tasks that overlap
+ * one another's outputs are rejected (FDBB_EALIAS). */
 int fdbb_batch_plan_create(const fdbb_task *tasks, int ntasks, int capacity, int block,
-                           int ppt, int grid, fdbb_batch_plan **plan);
+                           int ppt, int grid, int nontemporal, fdbb_batch_plan **plan);
 
 /* Replace the task list (ntasks <= capacity); stream-ordered on `stream`:
  * the upload happens before any later fdbb_batch_exec on the same stream. */

@@ -92,13 +92,13 @@ def riemann_task(U, R, gamma=1.4):
 class Plan:
     """Owner of one ``fdbb_batch_plan``."""
 
-    def __init__(self, tasks, capacity=None, block=256, ppt=1, grid=0):
+    def __init__(self, tasks, capacity=None, block=256, ppt=1, grid=0, nontemporal=1):
         lib = F.library()
         arr = (F.Task * max(1, len(tasks)))(*tasks)
         self.capacity = capacity or max(1, len(tasks))
         self._h = ctypes.c_void_p()
         F.check(lib.fdbb_batch_plan_create(arr, len(tasks), self.capacity, block, ppt, grid,
-                                           ctypes.byref(self._h)))
+                                           nontemporal, ctypes.byref(self._h)))
         self.block, self.ppt = block, ppt
 
     def update(self, tasks, stream=None):

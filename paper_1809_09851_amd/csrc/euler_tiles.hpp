@@ -68,21 +68,18 @@ __device__ __forceinline__ void load_run(const T *__restrict__ p, int cnt, bool 
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void put(T *p, T v)
+// Output stores: non-temporal (NT, streamed past the caches' normal
+// allocation policy) or regular; which one the HBM write path prefers is a
+// launch-configuration choice.
+template <bool NT, typename V>
+__device__ __forceinline__ void put(V *p, V v)
 {
-    __builtin_nontemporal_store(v, p);
-}
-
-template <typename T, int N>
-__device__ __forceinline__ void put(vec_t<T, N> *p, vec_t<T, N> v)
-{
-    __builtin_nontemporal_store(v, p);
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
 }
 
 // Store P consecutive FP64 values at p, rounded to T (cnt of them valid).
-// Stores are non-temporal: outputs are streamed and never re-read here.
-template <typename T, int P>
+template <typename T, int P, bool NT>
 __device__ __forceinline__ void store_run(T *__restrict__ p, int cnt, bool vec, const double *x)
 {
     if (vec && cnt == P) {
@@ -90,23 +87,23 @@ __device__ __forceinline__ void store_run(T *__restrict__ p, int cnt, bool vec, 
 #pragma unroll
         for (int c = 0; c < C::N; ++c) {
             if constexpr (C::W == 1) {
-                put<T>(p + c, (T)x[c]);
+                put<NT, T>(p + c, (T)x[c]);
             } else {
                 vec_t<T, C::W> v;
 #pragma unroll
                 for (int j = 0; j < C::W; ++j) v[j] = (T)x[c * C::W + j];
-                put<T, C::W>(reinterpret_cast<vec_t<T, C::W> *>(p + c * C::W), v);
+                put<NT, vec_t<T, C::W>>(reinterpret_cast<vec_t<T, C::W> *>(p + c * C::W), v);
             }
         }
     } else {
 #pragma unroll
         for (int j = 0; j < P; ++j)
-            if (j < cnt) put<T>(p + j, (T)x[j]);
+            if (j < cnt) put<NT, T>(p + j, (T)x[j]);
     }
 }
 
 // Per-thread view of one tile.
-template <typename T, int P>
+template <typename T, int P, bool NT>
 struct Lane {
     int64_t i;  // first point of this thread
     int cnt;    // valid points of this thread, 0..P
@@ -132,17 +129,17 @@ struct Lane {
     __device__ __forceinline__ void store(void *base, int64_t ld, int field, const double *x) const
     {
         T *b = static_cast<T *>(base) + i + field * ld;
-        store_run<T, P>(b, cnt, vec, x);
+        store_run<T, P, NT>(b, cnt, vec, x);
     }
 };
 
 // ------------------------------------------------------------ pointwise ops
 
-template <int D, typename T, int P>
+template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void tile_cons2prim(const Args &a, int64_t tile0)
 {
     constexpr int K = D + 2;
-    Lane<T, P> L(a, tile0);
+    Lane<T, P, NT> L(a, tile0);
     if (L.cnt == 0) return;
     double u[K][P];
     L.template load<K>(a.in0, a.ld_in0, u);
@@ -163,11 +160,11 @@ __device__ __forceinline__ void tile_cons2prim(const Args &a, int64_t tile0)
         if (k >= first) L.store(a.out0, a.ld_out0, k, out[k]);
 }
 
-template <int D, typename T, int P>
+template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void tile_prim2cons(const Args &a, int64_t tile0)
 {
     constexpr int K = D + 2;
-    Lane<T, P> L(a, tile0);
+    Lane<T, P, NT> L(a, tile0);
     if (L.cnt == 0) return;
     double w[K][P];
     L.template load<K>(a.in0, a.ld_in0, w);
@@ -187,11 +184,11 @@ __device__ __forceinline__ void tile_prim2cons(const Args &a, int64_t tile0)
         if (k >= first) L.store(a.out0, a.ld_out0, k, out[k]);
 }
 
-template <int D, typename T, int P>
+template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void tile_eos(const Args &a, int64_t tile0)
 {
     constexpr int K = D + 2;
-    Lane<T, P> L(a, tile0);
+    Lane<T, P, NT> L(a, tile0);
     if (L.cnt == 0) return;
     double u[K][P];
     L.template load<K>(a.in0, a.ld_in0, u);
@@ -209,11 +206,11 @@ __device__ __forceinline__ void tile_eos(const Args &a, int64_t tile0)
     if (a.out1) L.store(a.out1, 0, 0, c);
 }
 
-template <int D, typename T, int P>
+template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void tile_flux(const Args &a, int64_t tile0)
 {
     constexpr int K = D + 2;
-    Lane<T, P> L(a, tile0);
+    Lane<T, P, NT> L(a, tile0);
     if (L.cnt == 0) return;
     double u[K][P];
     L.template load<K>(a.in0, a.ld_in0, u);
@@ -238,8 +235,8 @@ __device__ __forceinline__ void tile_flux(const Args &a, int64_t tile0)
 }
 
 // Riemann invariants of every direction and the entropy, from a state.
-template <int D, typename T, int P>
-__device__ __forceinline__ void store_riemann(const Args &a, const Lane<T, P> &L, const State<D> (&s)[P],
+template <int D, typename T, int P, bool NT>
+__device__ __forceinline__ void store_riemann(const Args &a, const Lane<T, P, NT> &L, const State<D> (&s)[P],
                                               const double (&c)[P], void *R, int64_t ldR)
 {
 #pragma unroll
@@ -260,11 +257,11 @@ __device__ __forceinline__ void store_riemann(const Args &a, const Lane<T, P> &L
     L.store(R, ldR, 2 * D, en);
 }
 
-template <int D, typename T, int P>
+template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void tile_riemann(const Args &a, int64_t tile0)
 {
     constexpr int K = D + 2;
-    Lane<T, P> L(a, tile0);
+    Lane<T, P, NT> L(a, tile0);
     if (L.cnt == 0) return;
     double u[K][P];
     L.template load<K>(a.in0, a.ld_in0, u);
@@ -278,15 +275,15 @@ __device__ __forceinline__ void tile_riemann(const Args &a, int64_t tile0)
         s[j] = make_state<D>(a.gas, uj);
         c[j] = sound_speed<D>(a.gas, s[j]);
     }
-    store_riemann<D, T, P>(a, L, s, c, a.out0, a.ld_out0);
+    store_riemann<D, T, P, NT>(a, L, s, c, a.out0, a.ld_out0);
 }
 
 // W = (w-_dir, s, tangential v ascending, w+_dir).
-template <int D, typename T, int P>
+template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void tile_cons2char(const Args &a, int64_t tile0)
 {
     constexpr int K = D + 2;
-    Lane<T, P> L(a, tile0);
+    Lane<T, P, NT> L(a, tile0);
     if (L.cnt == 0) return;
     double u[K][P];
     L.template load<K>(a.in0, a.ld_in0, u);
@@ -320,11 +317,11 @@ __device__ __forceinline__ void tile_cons2char(const Args &a, int64_t tile0)
     for (int k = 0; k < K; ++k) L.store(a.out0, a.ld_out0, k, out[k]);
 }
 
-template <int D, typename T, int P>
+template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void tile_char2cons(const Args &a, int64_t tile0)
 {
     constexpr int K = D + 2;
-    Lane<T, P> L(a, tile0);
+    Lane<T, P, NT> L(a, tile0);
     if (L.cnt == 0) return;
     double w[K][P];
     L.template load<K>(a.in0, a.ld_in0, w);
@@ -358,11 +355,11 @@ __device__ __forceinline__ void tile_char2cons(const Args &a, int64_t tile0)
 }
 
 // Ubar = sum_d A_d^T Fbar_d (dir < 0) or A_dir^T Fbar (dir >= 0).
-template <int D, typename T, int P>
+template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void tile_adjoint(const Args &a, int64_t tile0)
 {
     constexpr int K = D + 2;
-    Lane<T, P> L(a, tile0);
+    Lane<T, P, NT> L(a, tile0);
     if (L.cnt == 0) return;
     double u[K][P];
     L.template load<K>(a.in0, a.ld_in0, u);
@@ -438,7 +435,7 @@ constexpr size_t jacobian_lds_bytes(int block)
 
 // Copy the wave's staged blocks (count elements of T, contiguous in LDS and
 // in global memory) with lane-contiguous 16-byte stores when allowed.
-template <typename T>
+template <typename T, bool NT>
 __device__ __forceinline__ void wave_copy_out(const T *lds, T *dst, int count, bool vec, int lane)
 {
     if (vec) {
@@ -446,10 +443,10 @@ __device__ __forceinline__ void wave_copy_out(const T *lds, T *dst, int count, b
         const int chunks = count / W;
         const vec_t<T, W> *src = reinterpret_cast<const vec_t<T, W> *>(lds);
         vec_t<T, W> *out = reinterpret_cast<vec_t<T, W> *>(dst);
-        for (int c = lane; c < chunks; c += kWave) put<T, W>(out + c, src[c]);
-        for (int e = chunks * W + lane; e < count; e += kWave) put<T>(dst + e, lds[e]);
+        for (int c = lane; c < chunks; c += kWave) put<NT, vec_t<T, W>>(out + c, src[c]);
+        for (int e = chunks * W + lane; e < count; e += kWave) put<NT, T>(dst + e, lds[e]);
     } else {
-        for (int e = lane; e < count; e += kWave) put<T>(dst + e, lds[e]);
+        for (int e = lane; e < count; e += kWave) put<NT, T>(dst + e, lds[e]);
     }
 }
 
@@ -457,12 +454,12 @@ __device__ __forceinline__ void wave_copy_out(const T *lds, T *dst, int count, b
 // may be NULL) and Riemann invariants (out2, may be NULL) of the same state.
 // `lds` is this workgroup's staging area of jacobian_lds_bytes(blockDim.x);
 // every thread of the workgroup must call this (it holds barriers).
-template <int D, typename T, int P>
+template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void tile_fused(const Args &a, int64_t tile0, T *lds)
 {
     constexpr int K = D + 2;
     constexpr int KK = K * K;
-    Lane<T, P> L(a, tile0);
+    Lane<T, P, NT> L(a, tile0);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     const int64_t wave0 = tile0 + (int64_t)wave * kWave * P;
@@ -494,7 +491,7 @@ __device__ __forceinline__ void tile_fused(const Args &a, int64_t tile0, T *lds)
         double c[P];
 #pragma unroll
         for (int j = 0; j < P; ++j) c[j] = sound_speed<D>(a.gas, s[j]);
-        store_riemann<D, T, P>(a, L, s, c, a.out2, a.ld_out2);
+        store_riemann<D, T, P, NT>(a, L, s, c, a.out2, a.ld_out2);
     }
     if (a.out1) {
         double phi[P], H[P];
@@ -520,7 +517,7 @@ __device__ __forceinline__ void tile_fused(const Args &a, int64_t tile0, T *lds)
             }
             __syncthreads();
             if (wave_pts > 0)
-                wave_copy_out<T>(region, A + (d * a.ld_out1 + wave0) * KK, wave_pts * KK, L.vec, lane);
+                wave_copy_out<T, NT>(region, A + (d * a.ld_out1 + wave0) * KK, wave_pts * KK, L.vec, lane);
             __syncthreads();
         }
     }

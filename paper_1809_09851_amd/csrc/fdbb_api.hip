@@ -69,6 +69,7 @@ struct Config {
     int block;
     int ppt;
     int grid_cap;
+    int nt;
 };
 
 std::atomic<uint64_t> g_cfg[FDBB_NUM_OPS][3][2];
@@ -76,7 +77,7 @@ std::once_flag g_cfg_once;
 
 uint64_t pack(const Config &c)
 {
-    return (uint64_t)(uint16_t)c.block | ((uint64_t)(uint8_t)c.ppt << 16) |
+    return (uint64_t)(uint16_t)c.block | ((uint64_t)(uint8_t)c.ppt << 16) | ((uint64_t)(c.nt ? 1 : 0) << 24) |
            ((uint64_t)(uint32_t)c.grid_cap << 32);
 }
 
@@ -85,6 +86,7 @@ Config unpack(uint64_t v)
     Config c;
     c.block = (int)(v & 0xffff);
     c.ppt = (int)((v >> 16) & 0xff);
+    c.nt = (int)((v >> 24) & 1);
     c.grid_cap = (int)(uint32_t)(v >> 32);
     return c;
 }
@@ -99,6 +101,7 @@ void init_configs()
                 c.block = 256;
                 c.ppt = jac ? 1 : (t == FDBB_F64 ? 2 : 4);
                 c.grid_cap = 0;
+                c.nt = 1;
                 g_cfg[op][d][t].store(pack(c));
             }
 }
@@ -109,10 +112,10 @@ Config get_config(int op, int dim, int dtype)
     return unpack(g_cfg[op][dim - 1][dtype].load(std::memory_order_relaxed));
 }
 
-bool config_ok(int block, int ppt, int grid_cap)
+bool config_ok(int block, int ppt, int grid_cap, int nt)
 {
     return block >= 64 && block <= 1024 && block % 64 == 0 && (ppt == 1 || ppt == 2 || ppt == 4) &&
-           grid_cap >= 0;
+           grid_cap >= 0 && (nt == 0 || nt == 1);
 }
 
 // ------------------------------------------------------------ validation
@@ -237,7 +240,7 @@ int family_of(int op)
     }
 }
 
-const void *kernel_for(int op, int dim, int dtype, int ppt)
+const void *kernel_for(int op, int dim, int dtype, int ppt, bool nt)
 {
     const int fam = family_of(op);
     switch (fam) {
@@ -245,11 +248,11 @@ const void *kernel_for(int op, int dim, int dtype, int ppt)
     case kFamPrim2Cons:
     case kFamEos:
     case kFamFlux:
-    case kFamRiemann: return kernel_pointwise(fam, dim, dtype, ppt);
+    case kFamRiemann: return kernel_pointwise(fam, dim, dtype, ppt, nt);
     case kFamCons2Char:
-    case kFamChar2Cons: return kernel_char(fam, dim, dtype, ppt);
-    case kFamFused: return kernel_fused(dim, dtype, ppt);
-    case kFamAdjoint: return kernel_adjoint(dim, dtype, ppt);
+    case kFamChar2Cons: return kernel_char(fam, dim, dtype, ppt, nt);
+    case kFamFused: return kernel_fused(dim, dtype, ppt, nt);
+    case kFamAdjoint: return kernel_adjoint(dim, dtype, ppt, nt);
     default: return nullptr;
     }
 }
@@ -282,7 +285,7 @@ int launch(Call &c, void *stream)
     if (vector_ok(c)) c.a.flags |= kFlagVector;
 
     const Config cfg = get_config(c.op, c.dim, c.dtype);
-    const void *fn = kernel_for(c.op, c.dim, c.dtype, cfg.ppt);
+    const void *fn = kernel_for(c.op, c.dim, c.dtype, cfg.ppt, cfg.nt != 0);
     if (!fn) return fail(FDBB_EINVAL, "no kernel for this configuration");
     DeviceInfo dev;
     rc = device_info(&dev);
@@ -505,18 +508,18 @@ int fdbb_flux_adjoint(int dim, int dir, double gamma, int dtype, const void *U, 
     return run(t, stream);
 }
 
-int fdbb_set_launch_config(int op, int dim, int dtype, int block, int ppt, int grid_cap)
+int fdbb_set_launch_config(int op, int dim, int dtype, int block, int ppt, int grid_cap, int nontemporal)
 {
     if (op < 0 || op >= FDBB_NUM_OPS || dim < 1 || dim > 3 || (dtype != FDBB_F64 && dtype != FDBB_F32))
         return fail(FDBB_EINVAL, "unknown op, dim or dtype");
-    if (!config_ok(block, ppt, grid_cap)) return fail(FDBB_EINVAL, "invalid launch configuration");
+    if (!config_ok(block, ppt, grid_cap, nontemporal)) return fail(FDBB_EINVAL, "invalid launch configuration");
     std::call_once(g_cfg_once, init_configs);
-    Config c{block, ppt, grid_cap};
+    Config c{block, ppt, grid_cap, nontemporal};
     g_cfg[op][dim - 1][dtype].store(pack(c));
     return FDBB_OK;
 }
 
-int fdbb_get_launch_config(int op, int dim, int dtype, int *block, int *ppt, int *grid_cap)
+int fdbb_get_launch_config(int op, int dim, int dtype, int *block, int *ppt, int *grid_cap, int *nontemporal)
 {
     if (op < 0 || op >= FDBB_NUM_OPS || dim < 1 || dim > 3 || (dtype != FDBB_F64 && dtype != FDBB_F32))
         return fail(FDBB_EINVAL, "unknown op, dim or dtype");
@@ -524,6 +527,7 @@ int fdbb_get_launch_config(int op, int dim, int dtype, int *block, int *ppt, int
     if (block) *block = c.block;
     if (ppt) *ppt = c.ppt;
     if (grid_cap) *grid_cap = c.grid_cap;
+    if (nontemporal) *nontemporal = c.nt;
     return FDBB_OK;
 }
 
@@ -683,13 +687,13 @@ void free_plan(fdbb_batch_plan *p)
 extern "C" {
 
 int fdbb_batch_plan_create(const fdbb_task *tasks, int ntasks, int capacity, int block, int ppt, int grid,
-                           fdbb_batch_plan **plan)
+                           int nontemporal, fdbb_batch_plan **plan)
 {
     g_last_error.clear();
     if (!plan) return fail(FDBB_EINVAL, "plan must not be NULL");
     *plan = nullptr;
     if (capacity < 1 || capacity < ntasks) return fail(FDBB_EINVAL, "capacity must be >= max(1, ntasks)");
-    if (!config_ok(block, ppt, grid)) return fail(FDBB_EINVAL, "invalid launch configuration");
+    if (!config_ok(block, ppt, grid, nontemporal)) return fail(FDBB_EINVAL, "invalid launch configuration");
     if (ntasks > 0 && !tasks) return fail(FDBB_EINVAL, "tasks must not be NULL");
     // Argument checks of every task come before any HIP call.
     for (int b = 0; b < ntasks; ++b) {
@@ -706,7 +710,7 @@ int fdbb_batch_plan_create(const fdbb_task *tasks, int ntasks, int capacity, int
     p->capacity = capacity;
     p->block = block;
     p->ppt = ppt;
-    p->kernel = kernel_batch(ppt);
+    p->kernel = kernel_batch(ppt, nontemporal != 0);
     (void)hipGetDevice(&p->device);
     // LDS for the largest Jacobian staging among the first task list.
     size_t lds = 0;

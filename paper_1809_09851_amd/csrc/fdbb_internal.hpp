@@ -35,15 +35,16 @@ enum Family : int {
     kNumFamilies
 };
 
-// Single-operation kernels: void k(Args a, int64_t ntiles).
-const void *kernel_pointwise(int family, int dim, int dtype, int ppt);
-const void *kernel_char(int family, int dim, int dtype, int ppt);
-const void *kernel_fused(int dim, int dtype, int ppt);
-const void *kernel_adjoint(int dim, int dtype, int ppt);
+// Single-operation kernels: void k(Args a, int64_t ntiles).  nt selects
+// non-temporal output stores.
+const void *kernel_pointwise(int family, int dim, int dtype, int ppt, bool nt);
+const void *kernel_char(int family, int dim, int dtype, int ppt, bool nt);
+const void *kernel_fused(int dim, int dtype, int ppt, bool nt);
+const void *kernel_adjoint(int dim, int dtype, int ppt, bool nt);
 
 // Persistent batch kernel: void k(const TaskDev*, const int64_t* prefix,
 // const int64_t* header).  header = {ntasks, ntiles}; prefix has ntasks + 1
 // entries, prefix[b] = first tile of task b.
-const void *kernel_batch(int ppt);
+const void *kernel_batch(int ppt, bool nt);
 
 }  // namespace fdbb

@@ -4,34 +4,40 @@
 
 namespace fdbb {
 
-template <int D, typename T, int P>
+template <int D, typename T, int P, bool NT>
 __global__ __launch_bounds__(1024) void k_adjoint(Args a, int64_t ntiles)
 {
     const int64_t tile_pts = (int64_t)blockDim.x * P;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) tile_adjoint<D, T, P>(a, t * tile_pts);
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) tile_adjoint<D, T, P, NT>(a, t * tile_pts);
 }
 
-template <int D, typename T>
+template <int D, typename T, bool NT>
 static const void *pick_p(int ppt)
 {
     switch (ppt) {
-    case 1: return (const void *)&k_adjoint<D, T, 1>;
-    case 2: return (const void *)&k_adjoint<D, T, 2>;
-    case 4: return (const void *)&k_adjoint<D, T, 4>;
+    case 1: return (const void *)&k_adjoint<D, T, 1, NT>;
+    case 2: return (const void *)&k_adjoint<D, T, 2, NT>;
+    case 4: return (const void *)&k_adjoint<D, T, 4, NT>;
     default: return nullptr;
     }
 }
 
-const void *kernel_adjoint(int dim, int dtype, int ppt)
+template <int D, typename T>
+static const void *pick_p(int ppt, bool nt)
+{
+    return nt ? pick_p<D, T, true>(ppt) : pick_p<D, T, false>(ppt);
+}
+
+const void *kernel_adjoint(int dim, int dtype, int ppt, bool nt)
 {
     if (dtype == 0) {
-        if (dim == 1) return pick_p<1, double>(ppt);
-        if (dim == 2) return pick_p<2, double>(ppt);
-        if (dim == 3) return pick_p<3, double>(ppt);
+        if (dim == 1) return pick_p<1, double>(ppt, nt);
+        if (dim == 2) return pick_p<2, double>(ppt, nt);
+        if (dim == 3) return pick_p<3, double>(ppt, nt);
     } else {
-        if (dim == 1) return pick_p<1, float>(ppt);
-        if (dim == 2) return pick_p<2, float>(ppt);
-        if (dim == 3) return pick_p<3, float>(ppt);
+        if (dim == 1) return pick_p<1, float>(ppt, nt);
+        if (dim == 2) return pick_p<2, float>(ppt, nt);
+        if (dim == 3) return pick_p<3, float>(ppt, nt);
     }
     return nullptr;
 }

@@ -7,25 +7,25 @@
 
 namespace fdbb {
 
-template <int D, typename T, int P>
+template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void run_tile(int op, const Args &a, int64_t tile0, unsigned char *smem)
 {
     switch (op) {
-    case 0: tile_cons2prim<D, T, P>(a, tile0); break;
-    case 1: tile_prim2cons<D, T, P>(a, tile0); break;
-    case 2: tile_eos<D, T, P>(a, tile0); break;
-    case 3: tile_flux<D, T, P>(a, tile0); break;
+    case 0: tile_cons2prim<D, T, P, NT>(a, tile0); break;
+    case 1: tile_prim2cons<D, T, P, NT>(a, tile0); break;
+    case 2: tile_eos<D, T, P, NT>(a, tile0); break;
+    case 3: tile_flux<D, T, P, NT>(a, tile0); break;
     case 4:
-    case 8: tile_fused<D, T, P>(a, tile0, reinterpret_cast<T *>(smem)); break;
-    case 5: tile_riemann<D, T, P>(a, tile0); break;
-    case 6: tile_cons2char<D, T, P>(a, tile0); break;
-    case 7: tile_char2cons<D, T, P>(a, tile0); break;
-    case 9: tile_adjoint<D, T, P>(a, tile0); break;
+    case 8: tile_fused<D, T, P, NT>(a, tile0, reinterpret_cast<T *>(smem)); break;
+    case 5: tile_riemann<D, T, P, NT>(a, tile0); break;
+    case 6: tile_cons2char<D, T, P, NT>(a, tile0); break;
+    case 7: tile_char2cons<D, T, P, NT>(a, tile0); break;
+    case 9: tile_adjoint<D, T, P, NT>(a, tile0); break;
     default: break;
     }
 }
 
-template <int P>
+template <int P, bool NT>
 __global__ __launch_bounds__(1024) void k_batch(const TaskDev *__restrict__ tasks,
                                                 const int64_t *__restrict__ prefix,
                                                 const int64_t *__restrict__ header)
@@ -44,23 +44,23 @@ __global__ __launch_bounds__(1024) void k_batch(const TaskDev *__restrict__ task
         const TaskDev &td = tasks[lo];
         const int64_t tile0 = (t - prefix[lo]) * tile_pts;
         if (td.dtype == 0) {
-            if (td.dim == 1) run_tile<1, double, P>(td.op, td.a, tile0, smem);
-            else if (td.dim == 2) run_tile<2, double, P>(td.op, td.a, tile0, smem);
-            else run_tile<3, double, P>(td.op, td.a, tile0, smem);
+            if (td.dim == 1) run_tile<1, double, P, NT>(td.op, td.a, tile0, smem);
+            else if (td.dim == 2) run_tile<2, double, P, NT>(td.op, td.a, tile0, smem);
+            else run_tile<3, double, P, NT>(td.op, td.a, tile0, smem);
         } else {
-            if (td.dim == 1) run_tile<1, float, P>(td.op, td.a, tile0, smem);
-            else if (td.dim == 2) run_tile<2, float, P>(td.op, td.a, tile0, smem);
-            else run_tile<3, float, P>(td.op, td.a, tile0, smem);
+            if (td.dim == 1) run_tile<1, float, P, NT>(td.op, td.a, tile0, smem);
+            else if (td.dim == 2) run_tile<2, float, P, NT>(td.op, td.a, tile0, smem);
+            else run_tile<3, float, P, NT>(td.op, td.a, tile0, smem);
         }
     }
 }
 
-const void *kernel_batch(int ppt)
+const void *kernel_batch(int ppt, bool nt)
 {
     switch (ppt) {
-    case 1: return (const void *)&k_batch<1>;
-    case 2: return (const void *)&k_batch<2>;
-    case 4: return (const void *)&k_batch<4>;
+    case 1: return nt ? (const void *)&k_batch<1, true> : (const void *)&k_batch<1, false>;
+    case 2: return nt ? (const void *)&k_batch<2, true> : (const void *)&k_batch<2, false>;
+    case 4: return nt ? (const void *)&k_batch<4, true> : (const void *)&k_batch<4, false>;
     default: return nullptr;
     }
 }

@@ -5,54 +5,60 @@
 
 namespace fdbb {
 
-template <int FAM, int D, typename T, int P>
+template <int FAM, int D, typename T, int P, bool NT>
 __global__ __launch_bounds__(1024) void k_pointwise(Args a, int64_t ntiles)
 {
     const int64_t tile_pts = (int64_t)blockDim.x * P;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t tile0 = t * tile_pts;
-        if constexpr (FAM == kFamCons2Prim) tile_cons2prim<D, T, P>(a, tile0);
-        else if constexpr (FAM == kFamPrim2Cons) tile_prim2cons<D, T, P>(a, tile0);
-        else if constexpr (FAM == kFamEos) tile_eos<D, T, P>(a, tile0);
-        else if constexpr (FAM == kFamFlux) tile_flux<D, T, P>(a, tile0);
-        else if constexpr (FAM == kFamRiemann) tile_riemann<D, T, P>(a, tile0);
+        if constexpr (FAM == kFamCons2Prim) tile_cons2prim<D, T, P, NT>(a, tile0);
+        else if constexpr (FAM == kFamPrim2Cons) tile_prim2cons<D, T, P, NT>(a, tile0);
+        else if constexpr (FAM == kFamEos) tile_eos<D, T, P, NT>(a, tile0);
+        else if constexpr (FAM == kFamFlux) tile_flux<D, T, P, NT>(a, tile0);
+        else if constexpr (FAM == kFamRiemann) tile_riemann<D, T, P, NT>(a, tile0);
     }
 }
 
-template <int FAM, int D, typename T>
+template <int FAM, int D, typename T, bool NT>
 static const void *pick_p(int ppt)
 {
     switch (ppt) {
-    case 1: return (const void *)&k_pointwise<FAM, D, T, 1>;
-    case 2: return (const void *)&k_pointwise<FAM, D, T, 2>;
-    case 4: return (const void *)&k_pointwise<FAM, D, T, 4>;
+    case 1: return (const void *)&k_pointwise<FAM, D, T, 1, NT>;
+    case 2: return (const void *)&k_pointwise<FAM, D, T, 2, NT>;
+    case 4: return (const void *)&k_pointwise<FAM, D, T, 4, NT>;
     default: return nullptr;
     }
 }
 
+template <int FAM, int D, typename T>
+static const void *pick_p(int ppt, bool nt)
+{
+    return nt ? pick_p<FAM, D, T, true>(ppt) : pick_p<FAM, D, T, false>(ppt);
+}
+
 template <int FAM>
-static const void *pick(int dim, int dtype, int ppt)
+static const void *pick(int dim, int dtype, int ppt, bool nt)
 {
     if (dtype == 0) {
-        if (dim == 1) return pick_p<FAM, 1, double>(ppt);
-        if (dim == 2) return pick_p<FAM, 2, double>(ppt);
-        if (dim == 3) return pick_p<FAM, 3, double>(ppt);
+        if (dim == 1) return pick_p<FAM, 1, double>(ppt, nt);
+        if (dim == 2) return pick_p<FAM, 2, double>(ppt, nt);
+        if (dim == 3) return pick_p<FAM, 3, double>(ppt, nt);
     } else {
-        if (dim == 1) return pick_p<FAM, 1, float>(ppt);
-        if (dim == 2) return pick_p<FAM, 2, float>(ppt);
-        if (dim == 3) return pick_p<FAM, 3, float>(ppt);
+        if (dim == 1) return pick_p<FAM, 1, float>(ppt, nt);
+        if (dim == 2) return pick_p<FAM, 2, float>(ppt, nt);
+        if (dim == 3) return pick_p<FAM, 3, float>(ppt, nt);
     }
     return nullptr;
 }
 
-const void *kernel_pointwise(int family, int dim, int dtype, int ppt)
+const void *kernel_pointwise(int family, int dim, int dtype, int ppt, bool nt)
 {
     switch (family) {
-    case kFamCons2Prim: return pick<kFamCons2Prim>(dim, dtype, ppt);
-    case kFamPrim2Cons: return pick<kFamPrim2Cons>(dim, dtype, ppt);
-    case kFamEos: return pick<kFamEos>(dim, dtype, ppt);
-    case kFamFlux: return pick<kFamFlux>(dim, dtype, ppt);
-    case kFamRiemann: return pick<kFamRiemann>(dim, dtype, ppt);
+    case kFamCons2Prim: return pick<kFamCons2Prim>(dim, dtype, ppt, nt);
+    case kFamPrim2Cons: return pick<kFamPrim2Cons>(dim, dtype, ppt, nt);
+    case kFamEos: return pick<kFamEos>(dim, dtype, ppt, nt);
+    case kFamFlux: return pick<kFamFlux>(dim, dtype, ppt, nt);
+    case kFamRiemann: return pick<kFamRiemann>(dim, dtype, ppt, nt);
     default: return nullptr;
     }
 }

@@ -72,15 +72,15 @@ def library():
             getattr(lib, name).argtypes = [_i, _i, _d, _i, _p, _i64, _p, _i64, _i64, _p]
         lib.fdbb_euler_fused.argtypes = [_i, _d, _i, _p, _i64, _p, _i64, _p, _i64, _p, _i64, _i64, _p]
         lib.fdbb_flux_adjoint.argtypes = [_i, _i, _d, _i, _p, _i64, _p, _i64, _p, _i64, _i64, _p]
-        lib.fdbb_set_launch_config.argtypes = [_i, _i, _i, _i, _i, _i]
+        lib.fdbb_set_launch_config.argtypes = [_i, _i, _i, _i, _i, _i, _i]
         lib.fdbb_get_launch_config.argtypes = [_i, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i),
-                                               ctypes.POINTER(_i)]
+                                               ctypes.POINTER(_i), ctypes.POINTER(_i)]
         lib.fdbb_status_string.argtypes = [_i]
         lib.fdbb_status_string.restype = ctypes.c_char_p
         lib.fdbb_last_error.argtypes = []
         lib.fdbb_last_error.restype = ctypes.c_char_p
         lib.fdbb_version.argtypes = []
-        lib.fdbb_batch_plan_create.argtypes = [ctypes.POINTER(Task), _i, _i, _i, _i, _i,
+        lib.fdbb_batch_plan_create.argtypes = [ctypes.POINTER(Task), _i, _i, _i, _i, _i, _i,
                                                ctypes.POINTER(_p)]
         lib.fdbb_batch_plan_update.argtypes = [_p, ctypes.POINTER(Task), _i, _p]
         lib.fdbb_batch_exec.argtypes = [_p, _p, _i]
@@ -90,6 +90,9 @@ def library():
         lib.fdbb_probe_write.argtypes = [_p, _i64, ctypes.c_uint64, _i, _p]
         lib.fdbb_probe_read.argtypes = [_p, _i64, _p, _i, _p]
         _lib = lib
+        if os.environ.get("FDBB_NO_TUNED_TABLE") != "1":
+            from . import tune
+            tune.apply_table()
     return _lib
 
 
@@ -252,17 +255,18 @@ def fdbb_flux_adjoint(dim, direction, gamma, U, Fbar, Ubar, n=None, stream=None)
                                       ub, ldub, n, _stream(stream)))
 
 
-def fdbb_set_launch_config(op, dim, dtype, block, ppt, grid_cap=0):
+def fdbb_set_launch_config(op, dim, dtype, block, ppt, grid_cap=0, nontemporal=1):
     op = OPS[op] if isinstance(op, str) else op
-    check(library().fdbb_set_launch_config(op, dim, dtype, block, ppt, grid_cap))
+    check(library().fdbb_set_launch_config(op, dim, dtype, block, ppt, grid_cap, nontemporal))
 
 
 def fdbb_get_launch_config(op, dim, dtype):
+    """(block, ppt, grid_cap, nontemporal) of (op, dim, dtype)."""
     op = OPS[op] if isinstance(op, str) else op
-    b, p, g = _i(), _i(), _i()
+    b, p, g, t = _i(), _i(), _i(), _i()
     check(library().fdbb_get_launch_config(op, dim, dtype, ctypes.byref(b), ctypes.byref(p),
-                                           ctypes.byref(g)))
-    return b.value, p.value, g.value
+                                           ctypes.byref(g), ctypes.byref(t)))
+    return b.value, p.value, g.value, t.value
 
 
 def fdbb_version() -> int:

@@ -1,0 +1,197 @@
+"""Launch-configuration autotuner.
+
+Searches workgroup size x points per thread x grid cap x store mode for an
+(op, dim, dtype) at a given problem size, timing each candidate with HIP
+events on the launch stream (median of repeated launches), and installs the
+fastest with ``fdbb_set_launch_config``.  Results are kept in a JSON table
+keyed by device architecture, HIP runtime version and (op, dim, dtype); the
+binding applies the table shipped next to the library when it loads it.
+
+    python -m paper_1809_09851_amd.tune --ops fused,flux_jacobian --dims 3 \\
+        --dtypes f64,f32 --n 16777216 --write paper_1809_09851_amd/tuned_gfx950.json
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import os
+import statistics
+import sys
+
+import torch
+
+from . import fdbb as F
+
+GAMMA = 1.4
+BLOCKS = (64, 128, 256, 512, 1024)
+PPTS = (1, 2, 4)
+GRID_CAPS = (0, 2048, 4096, 8192)
+STORE_MODES = (1, 0)
+DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_gfx950.json")
+DT = {"f64": (F.F64, torch.float64), "f32": (F.F32, torch.float32)}
+
+
+def arch_key() -> str:
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    arch = getattr(props, "gcnArchName", "unknown").split(":")[0]
+    return f"{arch}/hip{torch.version.hip}"
+
+
+def _state(dim, n, dtype):
+    """A valid conservative state built on the device (no host data needed)."""
+    V = F.empty_fields(dim + 2, n, dtype)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1234)
+    V[0].uniform_(0.5, 2.0, generator=g)
+    for k in range(dim):
+        V[1 + k].normal_(0.0, 0.5, generator=g)
+    V[dim + 1].uniform_(0.5, 2.0, generator=g)
+    U = F.empty_fields(dim + 2, n, dtype)
+    F.fdbb_prim2cons(dim, GAMMA, V, U)
+    return U
+
+
+def workload(op: str, dim: int, dtype, n: int):
+    """Inputs and outputs resident on the device; returns one launch as a
+    closure."""
+    K = dim + 2
+    U = _state(dim, n, dtype)
+    if op == "fused":
+        Fo, A, R = (F.empty_fields(K * dim, n, dtype), F.empty_blocks(dim, n, dtype),
+                    F.empty_fields(2 * dim + 1, n, dtype))
+        return lambda: F.fdbb_euler_fused(dim, GAMMA, U, Fo, A, R)
+    if op == "flux_jacobian":
+        A = F.empty_blocks(dim, n, dtype)
+        return lambda: F.fdbb_flux_jacobian(dim, GAMMA, U, A)
+    if op == "flux":
+        Fo = F.empty_fields(K * dim, n, dtype)
+        return lambda: F.fdbb_flux(dim, GAMMA, U, Fo)
+    if op == "cons2prim":
+        V = F.empty_fields(K, n, dtype)
+        return lambda: F.fdbb_cons2prim(dim, GAMMA, U, V)
+    if op == "prim2cons":
+        V = F.empty_fields(K, n, dtype)
+        return lambda: F.fdbb_prim2cons(dim, GAMMA, U, V)
+    if op == "eos":
+        p = torch.empty(n, dtype=dtype, device="cuda")
+        c = torch.empty(n, dtype=dtype, device="cuda")
+        return lambda: F.fdbb_eos(dim, GAMMA, U, p, c)
+    if op == "riemann_invariants":
+        R = F.empty_fields(2 * dim + 1, n, dtype)
+        return lambda: F.fdbb_riemann_invariants(dim, GAMMA, U, R)
+    if op == "cons2char":
+        W = F.empty_fields(K, n, dtype)
+        return lambda: F.fdbb_cons2char(dim, 0, GAMMA, U, W)
+    if op == "char2cons":
+        W = F.empty_fields(K, n, dtype)
+        F.fdbb_cons2char(dim, 0, GAMMA, U, W)
+        return lambda: F.fdbb_char2cons(dim, 0, GAMMA, W, U)
+    if op == "adjoint":
+        Fb = F.empty_fields(K * dim, n, dtype).normal_()
+        Ub = F.empty_fields(K, n, dtype)
+        return lambda: F.fdbb_flux_adjoint(dim, -1, GAMMA, U, Fb, Ub)
+    raise ValueError(op)
+
+
+def time_launch(fn, reps: int = 7, warmup: int = 2) -> float:
+    """Median milliseconds of one launch, HIP events on the current stream."""
+    for _ in range(warmup):
+        fn()
+    stream = torch.cuda.current_stream()
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    return statistics.median(times)
+
+
+def search(op: str, dim: int, dt: str, n: int, reps: int = 7, space=None, verbose=False):
+    """Time every candidate; returns [(ms, (block, ppt, grid_cap, nt))] sorted,
+    and leaves the fastest installed."""
+    code, dtype = DT[dt]
+    fn = workload(op, dim, dtype, n)
+    space = space or list(itertools.product(BLOCKS, PPTS, GRID_CAPS, STORE_MODES))
+    old = F.fdbb_get_launch_config(op, dim, code)
+    results = []
+    for cfg in space:
+        F.fdbb_set_launch_config(op, dim, code, *cfg)
+        try:
+            ms = time_launch(fn, reps)
+        except F.FdbbError:
+            continue  # e.g. more LDS than a workgroup may hold
+        results.append((ms, cfg))
+        if verbose:
+            print(f"  {op} {dim}d {dt} n={n} cfg={cfg} {ms:.4f} ms", file=sys.stderr, flush=True)
+    results.sort()
+    F.fdbb_set_launch_config(op, dim, code, *(results[0][1] if results else old))
+    return results
+
+
+def load_table(path: str = DEFAULT_TABLE):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return None
+
+
+def apply_table(path: str = DEFAULT_TABLE, key: str | None = None) -> int:
+    """Install the table's configurations for this device; returns how many."""
+    table = load_table(path)
+    if not table:
+        return 0
+    if key is None:
+        try:
+            key = arch_key()
+        except Exception:
+            return 0
+    entries = table.get(key) or {}
+    count = 0
+    for name, e in entries.items():
+        op, dim, dt = name.split("/")
+        code = DT[dt][0]
+        F.fdbb_set_launch_config(op, int(dim), code, e["block"], e["ppt"], e["grid_cap"], e["nt"])
+        count += 1
+    return count
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--ops", default="fused")
+    ap.add_argument("--dims", default="3")
+    ap.add_argument("--dtypes", default="f64,f32")
+    ap.add_argument("--n", type=int, default=1 << 24)
+    ap.add_argument("--reps", type=int, default=7)
+    ap.add_argument("--write", default=None, help="merge results into this JSON table")
+    ap.add_argument("--verbose", action="store_true")
+    args = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    key = arch_key()
+    table = (load_table(args.write) if args.write else None) or {}
+    entries = table.setdefault(key, {})
+    for op in args.ops.split(","):
+        for dim in (int(d) for d in args.dims.split(",")):
+            for dt in args.dtypes.split(","):
+                res = search(op, dim, dt, args.n, args.reps, verbose=args.verbose)
+                best_ms, (block, ppt, cap, nt) = res[0]
+                base = [ms for ms, cfg in res if cfg == (256, 1 if op in ("fused", "flux_jacobian") else
+                                                         (2 if dt == "f64" else 4), 0, 1)]
+                entries[f"{op}/{dim}/{dt}"] = {"block": block, "ppt": ppt, "grid_cap": cap, "nt": nt,
+                                               "ms": round(best_ms, 5), "n": args.n,
+                                               "default_ms": round(base[0], 5) if base else None,
+                                               "top5": [[round(ms, 5), list(c)] for ms, c in res[:5]]}
+                print(json.dumps({f"{op}/{dim}/{dt}": entries[f"{op}/{dim}/{dt}"]}), flush=True)
+    if args.write:
+        with open(args.write, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

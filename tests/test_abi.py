@@ -109,13 +109,15 @@ def test_direction_checks():
 
 
 def test_launch_config_table():
-    assert F.library().fdbb_set_launch_config(3, 3, 0, 100, 1, 0) == F.EINVAL   # not a multiple of 64
-    assert F.library().fdbb_set_launch_config(3, 3, 0, 256, 3, 0) == F.EINVAL   # ppt
-    assert F.library().fdbb_set_launch_config(3, 3, 0, 2048, 1, 0) == F.EINVAL
-    assert F.library().fdbb_set_launch_config(99, 3, 0, 256, 1, 0) == F.EINVAL
+    lib = F.library()
+    assert lib.fdbb_set_launch_config(3, 3, 0, 100, 1, 0, 1) == F.EINVAL   # not a multiple of 64
+    assert lib.fdbb_set_launch_config(3, 3, 0, 256, 3, 0, 1) == F.EINVAL   # ppt
+    assert lib.fdbb_set_launch_config(3, 3, 0, 2048, 1, 0, 1) == F.EINVAL
+    assert lib.fdbb_set_launch_config(3, 3, 0, 256, 1, 0, 2) == F.EINVAL   # store mode
+    assert lib.fdbb_set_launch_config(99, 3, 0, 256, 1, 0, 1) == F.EINVAL
     old = F.fdbb_get_launch_config("flux", 3, 0)
-    F.fdbb_set_launch_config("flux", 3, 0, 512, 4, 1000)
-    assert F.fdbb_get_launch_config("flux", 3, 0) == (512, 4, 1000)
+    F.fdbb_set_launch_config("flux", 3, 0, 512, 4, 1000, 0)
+    assert F.fdbb_get_launch_config("flux", 3, 0) == (512, 4, 1000, 0)
     F.fdbb_set_launch_config("flux", 3, 0, *old)
     assert F.fdbb_get_launch_config("flux", 3, 0) == old
 
@@ -125,7 +127,7 @@ def test_batch_plan_rejects_bad_tasks():
     plan = ctypes.c_void_p()
     t = (F.Task * 1)()
     t[0].op, t[0].dim, t[0].dtype, t[0].gamma, t[0].n = 3, 4, 0, 1.4, 10
-    assert lib.fdbb_batch_plan_create(t, 1, 1, 256, 1, 0, ctypes.byref(plan)) == F.EINVAL
-    assert lib.fdbb_batch_plan_create(t, 1, 0, 256, 1, 0, ctypes.byref(plan)) == F.EINVAL
-    assert lib.fdbb_batch_plan_create(t, 1, 1, 100, 1, 0, ctypes.byref(plan)) == F.EINVAL
+    assert lib.fdbb_batch_plan_create(t, 1, 1, 256, 1, 0, 1, ctypes.byref(plan)) == F.EINVAL
+    assert lib.fdbb_batch_plan_create(t, 1, 0, 256, 1, 0, 1, ctypes.byref(plan)) == F.EINVAL
+    assert lib.fdbb_batch_plan_create(t, 1, 1, 100, 1, 0, 1, ctypes.byref(plan)) == F.EINVAL
     assert not plan.value

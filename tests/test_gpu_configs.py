@@ -9,7 +9,7 @@ from paper_1809_09851_amd import fdbb as F
 
 pytestmark = pytest.mark.gpu
 
-CONFIGS = [(b, p, g) for b in (64, 128, 256, 512, 1024) for p in (1, 2, 4) for g in (0, 7)]
+CONFIGS = [(b, p, g, t) for b in (64, 128, 256, 512, 1024) for p in (1, 2, 4) for g, t in ((0, 1), (7, 0))]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -26,8 +26,8 @@ def _with_config(op, dim, dt_code, cfg, fn):
         F.fdbb_set_launch_config(op, dim, dt_code, *old)
 
 
-@pytest.mark.parametrize("block,ppt,grid", CONFIGS)
-def test_fused_all_configs(block, ppt, grid):
+@pytest.mark.parametrize("block,ppt,grid,nt", CONFIGS)
+def test_fused_all_configs(block, ppt, grid, nt):
     n = 7001
     for dt, code, es in (("f64", F.F64, 8), ("f32", F.F32, 4)):
         for dim in (1, 2, 3):
@@ -35,7 +35,7 @@ def test_fused_all_configs(block, ppt, grid):
             K = dim + 2
             lds = block * ppt * K * K * es
             try:
-                Fg, A, R = _with_config("fused", dim, code, (block, ppt, grid),
+                Fg, A, R = _with_config("fused", dim, code, (block, ppt, grid, nt),
                                         lambda: F.euler_fused(Ug, GAMMA))
             except F.FdbbError as e:
                 assert e.status == F.EINVAL and lds > 65536, (dt, dim, str(e))
@@ -46,17 +46,17 @@ def test_fused_all_configs(block, ppt, grid):
             assert group_error(host(R), Ro, riemann_groups(dim)) <= TOL[dt]
 
 
-@pytest.mark.parametrize("block,ppt,grid", CONFIGS)
-def test_pointwise_all_configs(block, ppt, grid):
+@pytest.mark.parametrize("block,ppt,grid,nt", CONFIGS)
+def test_pointwise_all_configs(block, ppt, grid, nt):
     n = 5003
     for dt, code in (("f64", F.F64), ("f32", F.F32)):
         dim = 3
         Uo, Ug = states(dim, n, 80, dt)
-        Fg = _with_config("flux", dim, code, (block, ppt, grid), lambda: F.flux(Ug, GAMMA))
+        Fg = _with_config("flux", dim, code, (block, ppt, grid, nt), lambda: F.flux(Ug, GAMMA))
         assert group_error(host(Fg), oracle.flux(dim, GAMMA, Uo), flux_groups(dim)) <= TOL[dt]
-        V = _with_config("cons2prim", dim, code, (block, ppt, grid), lambda: F.cons2prim(Ug, GAMMA))
+        V = _with_config("cons2prim", dim, code, (block, ppt, grid, nt), lambda: F.cons2prim(Ug, GAMMA))
         assert group_error(host(V), oracle.cons2prim(dim, GAMMA, Uo), state_groups(dim)) <= TOL[dt]
-        A = _with_config("flux_jacobian", dim, code, (block, ppt, grid), lambda: _try_jac(Ug))
+        A = _with_config("flux_jacobian", dim, code, (block, ppt, grid, nt), lambda: _try_jac(Ug))
         if A is not None:
             assert blocks_error(host(A), oracle.flux_jacobian(dim, GAMMA, Uo)) <= TOL[dt]
 
