@@ -228,6 +228,44 @@ def bench_adjoint(steps: int, warmup: int):
     return res
 
 
+def bench_autograd(steps: int, warmup: int):
+    """Forward + backward of EulerFlux (flux kernel, then adjoint kernel) on
+    the 3D N = 2^22 state with loss sum(w . F)."""
+    import torch
+    from paper_1809_09851_amd import fdbb as F
+    from paper_1809_09851_amd import inputs
+    from paper_1809_09851_amd.autograd import euler_flux
+    n, dim = 1 << 22, 3
+    U = device_state(dim, n, 3, torch.float64).requires_grad_(True)
+    w = F.to_fields(torch.from_numpy(inputs.cotangent(dim, n, 3)).cuda())
+
+    def step():
+        U.grad = None
+        (euler_flux(U, GAMMA) * w).sum().backward()
+
+    wall, ev = timed_launches(step, steps, warmup)
+    del U, w
+    torch.cuda.empty_cache()
+    return {"n": n, "ms_per_fwd_bwd": round(wall, 4), "gpoints_s": round(n / (wall * 1e-3) / 1e9, 3)}
+
+
+def bench_serving(rates, count: int, warmup: int):
+    """Poisson request streams: continuous batching against one launch per
+    request on a single stream (same requests, same pools)."""
+    from paper_1809_09851_amd import serve as S
+    pools = S.StatePools()
+    out = []
+    for rate in rates:
+        for baseline in (False, True):
+            r = S.serve_benchmark(rate, count, warmup=warmup, pools=pools, baseline=baseline)
+            print(f"# serving rate={rate:g} {'baseline' if baseline else 'batched'}: "
+                  f"p50 {r['p50_ms']} ms p99 {r['p99_ms']} ms, {r['req_s']} req/s",
+                  file=sys.stderr, flush=True)
+            out.append(r)
+    del pools
+    return out
+
+
 def bench_probes(steps: int, warmup: int, gib: float = 4.0):
     """What HBM delivers to plain streaming kernels: read, write, copy."""
     import torch
@@ -255,6 +293,10 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=1 << 24)
     ap.add_argument("--extras", action="store_true", help="also time the other building blocks")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--serve-rates", default="1000",
+                    help="comma-separated Poisson rates (req/s) for the serving measurement; '' skips it")
+    ap.add_argument("--serve-count", type=int, default=1000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run the 1 GiB copy probe 3 times (hardware byte-counter calibration)")
     args = ap.parse_args(argv)
@@ -308,8 +350,12 @@ def main(argv=None):
         ex["three_launches_3d_f64"] = {"gpoints_s": round(sep["gpoints_s"], 3)}
         ex["ops_1d_f64_2p20"] = bench_1d(args.steps, args.warmup)
         ex["adjoint_f64_2p22"] = bench_adjoint(args.steps, args.warmup)
+        ex["autograd_3d_f64_2p22"] = bench_autograd(max(5, args.steps // 5), 2)
         ex["hbm_probes_gbs"] = bench_probes(max(10, args.steps // 5), 3)
         line["extras"] = ex
+    rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
+    if rates:
+        line["serving"] = bench_serving(rates, args.serve_count, args.serve_warmup)
     if args.probe_copy:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
         b = torch.empty_like(a)

@@ -198,7 +198,10 @@ typedef struct fdbb_batch_plan fdbb_batch_plan;
  * HIP graph holding one persistent kernel with `grid` workgroups of `block`
  * threads (grid 0 picks one sized to the device), `ppt` points per thread
  * and non-temporal (1) or regular (0) output stores.  Tasks that overlap
- * one another's outputs are rejected (FDBB_EALIAS). */
+ * one another's outputs are rejected (FDBB_EALIAS).  Jacobian staging needs
+ * LDS; a plan holds what its first task list needs, or, when created with
+ * ntasks == 0, what any task needs (later task lists needing more than the
+ * plan holds are rejected with FDBB_EINVAL). */
 int fdbb_batch_plan_create(const fdbb_task *tasks, int ntasks, int capacity, int block,
                            int ppt, int grid, int nontemporal, fdbb_batch_plan **plan);
 

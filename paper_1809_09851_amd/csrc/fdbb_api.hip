@@ -712,8 +712,9 @@ int fdbb_batch_plan_create(const fdbb_task *tasks, int ntasks, int capacity, int
     p->ppt = ppt;
     p->kernel = kernel_batch(ppt, nontemporal != 0);
     (void)hipGetDevice(&p->device);
-    // LDS for the largest Jacobian staging among the first task list.
-    size_t lds = 0;
+    // LDS for the largest Jacobian staging among the first task list; a plan
+    // created empty reserves enough for any task (3D FP64 blocks).
+    size_t lds = ntasks == 0 ? lds_bytes(FDBB_OP_FLUX_JACOBIAN, 3, FDBB_F64, block, ppt) : 0;
     for (int b = 0; b < ntasks && tasks; ++b) {
         const bool jac = tasks[b].op == FDBB_OP_FLUX_JACOBIAN || (tasks[b].op == FDBB_OP_FUSED && tasks[b].out1);
         if (jac && tasks[b].dim >= 1 && tasks[b].dim <= 3 && (tasks[b].dtype == 0 || tasks[b].dtype == 1))

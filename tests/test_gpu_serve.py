@@ -1,0 +1,93 @@
+"""Serving on the GPU: each request's result is the same alone and in the
+mix, matches the oracle, and the budget holds."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_common import host, require_gpu
+from metrics import TOL, blocks_error, flux_groups, group_error, state_groups
+from paper_1809_09851_amd import inputs
+from paper_1809_09851_amd import serve as S
+
+pytestmark = pytest.mark.gpu
+GAMMA = 1.4
+
+
+@pytest.fixture(scope="module")
+def pools():
+    require_gpu()
+    return S.StatePools(pool=300_000, seed=4)
+
+
+def _specs(count, seed, rate):
+    return inputs.request_stream(rate, count, seed=seed, pool=300_000, lo_exp=2.0, hi_exp=5.3)
+
+
+def _check_oracle(r):
+    dt = "f64" if r.elem == 8 else "f32"
+    Uo = host(r.U)
+    if r.op == "cons2prim":
+        assert group_error(host(r.out), oracle.cons2prim(r.dim, GAMMA, Uo), state_groups(r.dim)) <= TOL[dt]
+    elif r.op == "flux":
+        assert group_error(host(r.out), oracle.flux(r.dim, GAMMA, Uo), flux_groups(r.dim)) <= TOL[dt]
+    elif r.op == "flux_jacobian":
+        assert blocks_error(host(r.out), oracle.flux_jacobian(r.dim, GAMMA, Uo)) <= TOL[dt]
+    else:
+        Fb = host(r.Fbar)
+        ref = oracle.flux_adjoint(r.dim, -1, GAMMA, Uo, Fb)
+        A = np.abs(oracle.flux_jacobian(r.dim, GAMMA, Uo))
+        K = r.dim + 2
+        den = np.zeros((K, r.n))
+        for d in range(r.dim):
+            den += np.einsum("nrc,rn->cn", A[d], np.abs(np.array([Fb[q * r.dim + d] for q in range(K)])))
+        assert group_error(host(r.out), ref, [list(range(K))], denom=den.max(axis=0)) <= TOL[dt]
+
+
+def test_alone_equals_mix_and_oracle(pools):
+    specs = _specs(48, 11, rate=2e4)
+    # in the mix: Poisson arrivals, 3 slots, batches of up to 16
+    ex = S.GpuBatchExecutor(3)
+    srv = S.Server(ex, 200 * 10 ** 9, slots=3, max_batch=16)
+    mixed = srv.run_arrivals([pools.request(s) for s in specs])
+    torch.cuda.synchronize()
+    assert len(mixed) == 48
+    assert srv.launches < 48  # requests were batched
+    by_id = {r.rid: r for r in mixed}
+    # alone: a fresh server per request
+    for k, s in enumerate(specs[:16]):
+        ex1 = S.GpuBatchExecutor(1)
+        s1 = S.Server(ex1, 200 * 10 ** 9, slots=1)
+        (alone,) = s1.run_arrivals([pools.request(s)])
+        torch.cuda.synchronize()
+        assert torch.equal(alone.out, by_id[k].out), f"request {k} ({s['op']}) differs alone vs mix"
+        ex1.close()
+    for r in mixed:
+        _check_oracle(r)
+    ex.close()
+
+
+def test_budget_holds_under_pressure(pools):
+    specs = _specs(40, 12, rate=1e5)
+    reqs = [pools.request(s) for s in specs]
+    budget = 2 * max(r.out_bytes for r in reqs)
+    ex = S.GpuBatchExecutor(4)
+    srv = S.Server(ex, budget, slots=4, max_batch=8)
+    done = srv.run_arrivals(reqs)
+    torch.cuda.synchronize()
+    assert len(done) == 40
+    assert srv.peak_used <= budget
+    for r in done[:10]:
+        _check_oracle(r)
+    ex.close()
+
+
+def test_baseline_executor_matches_oracle(pools):
+    specs = _specs(12, 13, rate=1e4)
+    ex = S.SingleLaunchExecutor()
+    srv = S.Server(ex, 200 * 10 ** 9, slots=None, max_batch=1)
+    done = srv.run_arrivals([pools.request(s) for s in specs])
+    torch.cuda.synchronize()
+    assert srv.launches == 12
+    for r in done:
+        _check_oracle(r)
