@@ -153,7 +153,8 @@ int fdbb_flux_adjoint(int dim, int dir, double gamma, int dtype, const void *U, 
 
 /* ---------------------------------------------------------------- tuning
  * Launch configuration per (op, dim, dtype): `block` threads per workgroup
- * (64..1024, a multiple of 64), `ppt` consecutive points per thread
+ * (64..1024, a multiple of 64; at most 256 for the flux Jacobian and the
+ * fused pass, whose kernels stage blocks in LDS), `ppt` points per thread
  * (1, 2 or 4), `grid_cap` the largest grid (0 = one tile per workgroup;
  * otherwise workgroups loop over tiles) and `nontemporal` (1: outputs are
  * written with non-temporal stores, 0: regular stores).  Returns
@@ -163,6 +164,13 @@ int fdbb_set_launch_config(int op, int dim, int dtype, int block, int ppt, int g
                            int nontemporal);
 int fdbb_get_launch_config(int op, int dim, int dtype, int *block, int *ppt, int *grid_cap,
                            int *nontemporal);
+
+/* Resources of the kernel that (op, dim, dtype, ppt, nontemporal) launches:
+ * vector registers per thread and private (spill) bytes per thread, which
+ * cost memory traffic when non-zero.  Either output may be NULL.  Queries
+ * the HIP runtime (FDBB_EHIP if that fails). */
+int fdbb_kernel_info(int op, int dim, int dtype, int ppt, int nontemporal, int *vgprs,
+                     int *scratch_bytes);
 
 /* ---------------------------------------------------------------- batches
  * Many independent blocks of uneven size in one persistent launch.  A task
@@ -196,7 +204,7 @@ typedef struct fdbb_batch_plan fdbb_batch_plan;
  * into it.  Each task is validated as its single-call entry point would be.
  * The plan owns a device copy of the task table, the tile prefix sums and a
  * HIP graph holding one persistent kernel with `grid` workgroups of `block`
- * threads (grid 0 picks one sized to the device), `ppt` points per thread
+ * threads (64..256; grid 0 picks one sized to the device), `ppt` points per thread
  * and non-temporal (1) or regular (0) output stores.  Tasks that overlap
  * one another's outputs are rejected (FDBB_EALIAS).  Jacobian staging needs
  * LDS; a plan holds what its first task list needs, or, when created with

@@ -107,29 +107,29 @@ __device__ __forceinline__ double flux_entry(const State<D> &s, int r, int d)
 //                  delta_ij v_d + delta_jd v_i - (gamma-1) delta_id v_j,
 //                  (gamma-1) delta_id]
 //   row D+1     : [v_d (phi - H), delta_jd H - (gamma-1) v_j v_d, gamma v_d]
-// r, c and d are compile-time constants after unrolling, so every branch
-// folds away.
+// v is the velocity of the point.  r, c and d are compile-time constants
+// after unrolling, so every branch folds away.
 template <int D>
-__device__ __forceinline__ double jacobian_entry(const Gas &g, const State<D> &s, double phi,
-                                                 double H, int d, int r, int c)
+__device__ __forceinline__ double jacobian_entry(const Gas &g, const double *v, double phi, double H, int d,
+                                                 int r, int c)
 {
     constexpr int K = D + 2;
     if (r == 0) return (c == 1 + d) ? 1.0 : 0.0;
     if (r == K - 1) {
-        if (c == 0) return s.v[d] * (phi - H);
-        if (c == K - 1) return g.gamma * s.v[d];
+        if (c == 0) return v[d] * (phi - H);
+        if (c == K - 1) return g.gamma * v[d];
         const int j = c - 1;
-        const double t = -g.g1 * s.v[j] * s.v[d];
+        const double t = -g.g1 * v[j] * v[d];
         return (j == d) ? t + H : t;
     }
     const int i = r - 1;
-    if (c == 0) return (i == d) ? phi - s.v[i] * s.v[d] : -s.v[i] * s.v[d];
+    if (c == 0) return (i == d) ? phi - v[i] * v[d] : -v[i] * v[d];
     if (c == K - 1) return (i == d) ? g.g1 : 0.0;
     const int j = c - 1;
     double t = 0.0;
-    if (i == j) t += s.v[d];
-    if (j == d) t += s.v[i];
-    if (i == d) t -= g.g1 * s.v[j];
+    if (i == j) t += v[d];
+    if (j == d) t += v[i];
+    if (i == d) t -= g.g1 * v[j];
     return t;
 }
 

@@ -1,10 +1,10 @@
 // Tile code: one workgroup evaluates one tile of blockDim.x * P consecutive
-// points.  Thread t of the workgroup owns the P consecutive points starting
-// at tile0 + t * P, so every SoA field is read and written as one contiguous
-// run of blockDim.x * P elements (16-byte vector accesses per lane when the
-// call's pointers allow it).  The flux Jacobian blocks, which are stored
-// point-major (K*K contiguous values per point), are staged through a
-// per-wave LDS region and written out as contiguous runs of 16-byte stores.
+// points; each wave takes 64 * P of them and each thread P (see Lane), laid
+// out so that every SoA field is read and written as whole contiguous runs
+// (16-byte vector accesses per lane when the call's pointers allow it).  The
+// flux Jacobian blocks, which are stored point-major (K*K contiguous values
+// per point), are staged through a per-wave LDS region and written out as
+// contiguous runs of 16-byte stores.
 #pragma once
 
 #include "euler_point.hpp"
@@ -39,32 +39,30 @@ struct Args {
 template <typename T, int N>
 using vec_t = T __attribute__((ext_vector_type(N)));
 
-// Elements of T per 16-byte chunk, capped at P.
+// Points per chunk (at most two: 16 bytes of FP64, 8 of FP32) and chunks
+// per thread.  A chunk is the unit of one vector access and of the FP64
+// per-point state held in registers at one time.
 template <typename T, int P>
 struct Chunk {
-    static constexpr int W = (P * (int)sizeof(T) > 16) ? 16 / (int)sizeof(T) : P;
+    static constexpr int W = P >= 2 ? 2 : 1;
     static constexpr int N = P / W;
 };
 
-// Load the P consecutive values at p (cnt of them valid) widened to FP64.
-template <typename T, int P>
-__device__ __forceinline__ void load_run(const T *__restrict__ p, int cnt, bool vec, double *x)
+// Load the W consecutive values at p (cnt of them valid) widened to FP64.
+template <typename T, int W>
+__device__ __forceinline__ void load_chunk(const T *__restrict__ p, int cnt, bool vec, double *x)
 {
-    if (vec && cnt == P) {
-        using C = Chunk<T, P>;
+    if (vec && cnt == W) {
+        if constexpr (W == 1) {
+            x[0] = (double)p[0];
+        } else {
+            const vec_t<T, W> v = *reinterpret_cast<const vec_t<T, W> *>(p);
 #pragma unroll
-        for (int c = 0; c < C::N; ++c) {
-            if constexpr (C::W == 1) {
-                x[c] = (double)p[c];
-            } else {
-                const vec_t<T, C::W> v = *reinterpret_cast<const vec_t<T, C::W> *>(p + c * C::W);
-#pragma unroll
-                for (int j = 0; j < C::W; ++j) x[c * C::W + j] = (double)v[j];
-            }
+            for (int j = 0; j < W; ++j) x[j] = (double)v[j];
         }
     } else {
 #pragma unroll
-        for (int j = 0; j < P; ++j) x[j] = (j < cnt) ? (double)p[j] : 1.0;
+        for (int j = 0; j < W; ++j) x[j] = (j < cnt) ? (double)p[j] : 1.0;
     }
 }
 
@@ -78,204 +76,274 @@ __device__ __forceinline__ void put(V *p, V v)
     else *p = v;
 }
 
-// Store P consecutive FP64 values at p, rounded to T (cnt of them valid).
-template <typename T, int P, bool NT>
-__device__ __forceinline__ void store_run(T *__restrict__ p, int cnt, bool vec, const double *x)
+// Store W consecutive FP64 values at p, rounded to T (cnt of them valid).
+template <typename T, int W, bool NT>
+__device__ __forceinline__ void store_chunk(T *__restrict__ p, int cnt, bool vec, const double *x)
 {
-    if (vec && cnt == P) {
-        using C = Chunk<T, P>;
+    if (vec && cnt == W) {
+        if constexpr (W == 1) {
+            put<NT, T>(p, (T)x[0]);
+        } else {
+            vec_t<T, W> v;
 #pragma unroll
-        for (int c = 0; c < C::N; ++c) {
-            if constexpr (C::W == 1) {
-                put<NT, T>(p + c, (T)x[c]);
-            } else {
-                vec_t<T, C::W> v;
-#pragma unroll
-                for (int j = 0; j < C::W; ++j) v[j] = (T)x[c * C::W + j];
-                put<NT, vec_t<T, C::W>>(reinterpret_cast<vec_t<T, C::W> *>(p + c * C::W), v);
-            }
+            for (int j = 0; j < W; ++j) v[j] = (T)x[j];
+            put<NT, vec_t<T, W>>(reinterpret_cast<vec_t<T, W> *>(p), v);
         }
     } else {
 #pragma unroll
-        for (int j = 0; j < P; ++j)
+        for (int j = 0; j < W; ++j)
             if (j < cnt) put<NT, T>(p + j, (T)x[j]);
     }
 }
 
-// Per-thread view of one tile.
+// Per-thread view of one tile.  Wave w of the workgroup covers the 64 * P
+// consecutive points starting at tile0 + w * 64 * P.  A thread owns P of
+// them as P / W chunks of W consecutive points (W * sizeof(T) <= 16 bytes);
+// chunk c of lane l starts at wave point c * 64 * W + l * W, so every load
+// or store instruction of a wave covers one contiguous run of 64 * W
+// points (whole cache lines), whatever P is.
 template <typename T, int P, bool NT>
 struct Lane {
-    int64_t i;  // first point of this thread
-    int cnt;    // valid points of this thread, 0..P
+    static constexpr int W = Chunk<T, P>::W;
+    static constexpr int NC = Chunk<T, P>::N;
+    static constexpr int CS = kWave * W;  // points between a thread's chunks
+
+    int64_t i;     // first point of this thread's first chunk
+    int64_t left;  // points from i to the end of the range
+    int lane;
     bool vec;
 
     __device__ __forceinline__ Lane(const Args &a, int64_t tile0)
     {
-        i = tile0 + (int64_t)threadIdx.x * P;
-        const int64_t left = a.n - i;
-        cnt = left <= 0 ? 0 : (left >= P ? P : (int)left);
+        lane = threadIdx.x & (kWave - 1);
+        const int wave = threadIdx.x / kWave;
+        i = tile0 + (int64_t)wave * kWave * P + (int64_t)lane * W;
+        left = a.n - i;
         vec = (a.flags & kFlagVector) != 0;
     }
 
-    // Load `fields` consecutive fields of a field set into x[field][P].
-    template <int FIELDS>
-    __device__ __forceinline__ void load(const void *base, int64_t ld, double (&x)[FIELDS][P]) const
+    __device__ __forceinline__ bool any() const { return left > 0; }
+
+    // Valid points of chunk c.
+    __device__ __forceinline__ int count(int c) const
     {
-        const T *b = static_cast<const T *>(base) + i;
-#pragma unroll
-        for (int k = 0; k < FIELDS; ++k) load_run<T, P>(b + k * ld, cnt, vec, x[k]);
+        const int64_t l = left - (int64_t)c * CS;
+        return l <= 0 ? 0 : (l >= W ? W : (int)l);
     }
 
-    __device__ __forceinline__ void store(void *base, int64_t ld, int field, const double *x) const
+    // Position, inside the wave's 64 * P points, of the thread's point j.
+    __device__ __forceinline__ int local(int j) const { return (j / W) * CS + lane * W + (j % W); }
+
+    // Chunk c (W values) of field `field` of a field set with row stride ld.
+    __device__ __forceinline__ void load(const void *base, int64_t ld, int field, int c, double *x) const
     {
-        T *b = static_cast<T *>(base) + i + field * ld;
-        store_run<T, P, NT>(b, cnt, vec, x);
+        const T *b = static_cast<const T *>(base) + i + (int64_t)field * ld + c * CS;
+        load_chunk<T, W>(b, count(c), vec, x);
+    }
+
+    // Chunk c of `FIELDS` consecutive fields into x[field][W].
+    template <int FIELDS>
+    __device__ __forceinline__ void load_fields(const void *base, int64_t ld, int c,
+                                                double (&x)[FIELDS][W]) const
+    {
+#pragma unroll
+        for (int k = 0; k < FIELDS; ++k) load(base, ld, k, c, x[k]);
+    }
+
+    __device__ __forceinline__ void store(void *base, int64_t ld, int field, int c, const double *x) const
+    {
+        T *b = static_cast<T *>(base) + i + (int64_t)field * ld + c * CS;
+        store_chunk<T, W, NT>(b, count(c), vec, x);
     }
 };
 
+
 // ------------------------------------------------------------ pointwise ops
+//
+// Every op loads all of a thread's chunks first (so that the loads are in
+// flight together) and then evaluates and stores chunk by chunk, holding the
+// FP64 state of at most W points at a time.
 
 template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void tile_cons2prim(const Args &a, int64_t tile0)
 {
     constexpr int K = D + 2;
-    Lane<T, P, NT> L(a, tile0);
-    if (L.cnt == 0) return;
-    double u[K][P];
-    L.template load<K>(a.in0, a.ld_in0, u);
-    double out[K][P];
+    using L_t = Lane<T, P, NT>;
+    constexpr int W = L_t::W, NC = L_t::NC;
+    const L_t L(a, tile0);
+    if (!L.any()) return;
+    double u[NC][K][W];
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-        double uj[K], vj[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) uj[k] = u[k][j];
-        const State<D> s = make_state<D>(a.gas, uj);
-        to_primitive<D>(s, vj);
-#pragma unroll
-        for (int k = 0; k < K; ++k) out[k][j] = vj[k];
-    }
+    for (int c = 0; c < NC; ++c) L.template load_fields<K>(a.in0, a.ld_in0, c, u[c]);
     const int first = (a.flags & kFlagInPlace) ? 1 : 0;
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-        if (k >= first) L.store(a.out0, a.ld_out0, k, out[k]);
+    for (int c = 0; c < NC; ++c) {
+        double out[K][W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            double uj[K], vj[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) uj[k] = u[c][k][j];
+            to_primitive<D>(make_state<D>(a.gas, uj), vj);
+#pragma unroll
+            for (int k = 0; k < K; ++k) out[k][j] = vj[k];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (k >= first) L.store(a.out0, a.ld_out0, k, c, out[k]);
+    }
 }
 
 template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void tile_prim2cons(const Args &a, int64_t tile0)
 {
     constexpr int K = D + 2;
-    Lane<T, P, NT> L(a, tile0);
-    if (L.cnt == 0) return;
-    double w[K][P];
-    L.template load<K>(a.in0, a.ld_in0, w);
-    double out[K][P];
+    using L_t = Lane<T, P, NT>;
+    constexpr int W = L_t::W, NC = L_t::NC;
+    const L_t L(a, tile0);
+    if (!L.any()) return;
+    double w[NC][K][W];
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-        double vj[K], uj[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) vj[k] = w[k][j];
-        from_primitive<D>(a.gas, vj, uj);
-#pragma unroll
-        for (int k = 0; k < K; ++k) out[k][j] = uj[k];
-    }
+    for (int c = 0; c < NC; ++c) L.template load_fields<K>(a.in0, a.ld_in0, c, w[c]);
     const int first = (a.flags & kFlagInPlace) ? 1 : 0;
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-        if (k >= first) L.store(a.out0, a.ld_out0, k, out[k]);
+    for (int c = 0; c < NC; ++c) {
+        double out[K][W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            double vj[K], uj[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) vj[k] = w[c][k][j];
+            from_primitive<D>(a.gas, vj, uj);
+#pragma unroll
+            for (int k = 0; k < K; ++k) out[k][j] = uj[k];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (k >= first) L.store(a.out0, a.ld_out0, k, c, out[k]);
+    }
 }
 
 template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void tile_eos(const Args &a, int64_t tile0)
 {
     constexpr int K = D + 2;
-    Lane<T, P, NT> L(a, tile0);
-    if (L.cnt == 0) return;
-    double u[K][P];
-    L.template load<K>(a.in0, a.ld_in0, u);
-    double p[P], c[P];
+    using L_t = Lane<T, P, NT>;
+    constexpr int W = L_t::W, NC = L_t::NC;
+    const L_t L(a, tile0);
+    if (!L.any()) return;
+    double u[NC][K][W];
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-        double uj[K];
+    for (int c = 0; c < NC; ++c) L.template load_fields<K>(a.in0, a.ld_in0, c, u[c]);
 #pragma unroll
-        for (int k = 0; k < K; ++k) uj[k] = u[k][j];
-        const State<D> s = make_state<D>(a.gas, uj);
-        p[j] = s.p;
-        c[j] = sound_speed<D>(a.gas, s);
+    for (int c = 0; c < NC; ++c) {
+        double p[W], cs[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            double uj[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) uj[k] = u[c][k][j];
+            const State<D> s = make_state<D>(a.gas, uj);
+            p[j] = s.p;
+            cs[j] = sound_speed<D>(a.gas, s);
+        }
+        if (a.out0) L.store(a.out0, 0, 0, c, p);
+        if (a.out1) L.store(a.out1, 0, 0, c, cs);
     }
-    if (a.out0) L.store(a.out0, 0, 0, p);
-    if (a.out1) L.store(a.out1, 0, 0, c);
+}
+
+// The K*D flux fields of W points.
+template <int D, typename T, int P, bool NT>
+__device__ __forceinline__ void store_flux(const Lane<T, P, NT> &L, const State<D> *s, int c, void *F,
+                                           int64_t ldF)
+{
+    constexpr int W = Lane<T, P, NT>::W;
+#pragma unroll
+    for (int r = 0; r < D + 2; ++r) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            double f[W];
+#pragma unroll
+            for (int j = 0; j < W; ++j) f[j] = flux_entry<D>(s[j], r, d);
+            L.store(F, ldF, r * D + d, c, f);
+        }
+    }
+}
+
+// Riemann invariants of every direction and the entropy, of W points.
+template <int D, typename T, int P, bool NT>
+__device__ __forceinline__ void store_riemann(const Args &a, const Lane<T, P, NT> &L, const State<D> *s, int c,
+                                              void *R, int64_t ldR)
+{
+    constexpr int W = Lane<T, P, NT>::W;
+    double t[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) t[j] = a.gas.two_inv_g1 * sound_speed<D>(a.gas, s[j]);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        double wm[W], wp[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            wm[j] = s[j].v[d] - t[j];
+            wp[j] = s[j].v[d] + t[j];
+        }
+        L.store(R, ldR, 2 * d, c, wm);
+        L.store(R, ldR, 2 * d + 1, c, wp);
+    }
+    double en[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) en[j] = entropy<D>(a.gas, s[j]);
+    L.store(R, ldR, 2 * D, c, en);
 }
 
 template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void tile_flux(const Args &a, int64_t tile0)
 {
     constexpr int K = D + 2;
-    Lane<T, P, NT> L(a, tile0);
-    if (L.cnt == 0) return;
-    double u[K][P];
-    L.template load<K>(a.in0, a.ld_in0, u);
-    State<D> s[P];
+    using L_t = Lane<T, P, NT>;
+    constexpr int W = L_t::W, NC = L_t::NC;
+    const L_t L(a, tile0);
+    if (!L.any()) return;
+    double u[NC][K][W];
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-        double uj[K];
+    for (int c = 0; c < NC; ++c) L.template load_fields<K>(a.in0, a.ld_in0, c, u[c]);
 #pragma unroll
-        for (int k = 0; k < K; ++k) uj[k] = u[k][j];
-        s[j] = make_state<D>(a.gas, uj);
-    }
+    for (int c = 0; c < NC; ++c) {
+        State<D> s[W];
 #pragma unroll
-    for (int r = 0; r < K; ++r) {
+        for (int j = 0; j < W; ++j) {
+            double uj[K];
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            double f[P];
-#pragma unroll
-            for (int j = 0; j < P; ++j) f[j] = flux_entry<D>(s[j], r, d);
-            L.store(a.out0, a.ld_out0, r * D + d, f);
+            for (int k = 0; k < K; ++k) uj[k] = u[c][k][j];
+            s[j] = make_state<D>(a.gas, uj);
         }
+        store_flux<D, T, P, NT>(L, s, c, a.out0, a.ld_out0);
     }
-}
-
-// Riemann invariants of every direction and the entropy, from a state.
-template <int D, typename T, int P, bool NT>
-__device__ __forceinline__ void store_riemann(const Args &a, const Lane<T, P, NT> &L, const State<D> (&s)[P],
-                                              const double (&c)[P], void *R, int64_t ldR)
-{
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        double wm[P], wp[P];
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-            const double t = a.gas.two_inv_g1 * c[j];
-            wm[j] = s[j].v[d] - t;
-            wp[j] = s[j].v[d] + t;
-        }
-        L.store(R, ldR, 2 * d, wm);
-        L.store(R, ldR, 2 * d + 1, wp);
-    }
-    double en[P];
-#pragma unroll
-    for (int j = 0; j < P; ++j) en[j] = entropy<D>(a.gas, s[j]);
-    L.store(R, ldR, 2 * D, en);
 }
 
 template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void tile_riemann(const Args &a, int64_t tile0)
 {
     constexpr int K = D + 2;
-    Lane<T, P, NT> L(a, tile0);
-    if (L.cnt == 0) return;
-    double u[K][P];
-    L.template load<K>(a.in0, a.ld_in0, u);
-    State<D> s[P];
-    double c[P];
+    using L_t = Lane<T, P, NT>;
+    constexpr int W = L_t::W, NC = L_t::NC;
+    const L_t L(a, tile0);
+    if (!L.any()) return;
+    double u[NC][K][W];
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-        double uj[K];
+    for (int c = 0; c < NC; ++c) L.template load_fields<K>(a.in0, a.ld_in0, c, u[c]);
 #pragma unroll
-        for (int k = 0; k < K; ++k) uj[k] = u[k][j];
-        s[j] = make_state<D>(a.gas, uj);
-        c[j] = sound_speed<D>(a.gas, s[j]);
+    for (int c = 0; c < NC; ++c) {
+        State<D> s[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            double uj[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) uj[k] = u[c][k][j];
+            s[j] = make_state<D>(a.gas, uj);
+        }
+        store_riemann<D, T, P, NT>(a, L, s, c, a.out0, a.ld_out0);
     }
-    store_riemann<D, T, P, NT>(a, L, s, c, a.out0, a.ld_out0);
 }
 
 // W = (w-_dir, s, tangential v ascending, w+_dir).
@@ -283,110 +351,125 @@ template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void tile_cons2char(const Args &a, int64_t tile0)
 {
     constexpr int K = D + 2;
-    Lane<T, P, NT> L(a, tile0);
-    if (L.cnt == 0) return;
-    double u[K][P];
-    L.template load<K>(a.in0, a.ld_in0, u);
-    double out[K][P];
+    using L_t = Lane<T, P, NT>;
+    constexpr int W = L_t::W, NC = L_t::NC;
+    const L_t L(a, tile0);
+    if (!L.any()) return;
+    double u[NC][K][W];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) L.template load_fields<K>(a.in0, a.ld_in0, c, u[c]);
     const int dir = a.dir;
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-        double uj[K];
+    for (int c = 0; c < NC; ++c) {
+        double out[K][W];
 #pragma unroll
-        for (int k = 0; k < K; ++k) uj[k] = u[k][j];
-        const State<D> s = make_state<D>(a.gas, uj);
-        const double t = a.gas.two_inv_g1 * sound_speed<D>(a.gas, s);
-        double vd = s.v[0];
+        for (int j = 0; j < W; ++j) {
+            double uj[K];
 #pragma unroll
-        for (int k = 1; k < D; ++k)
-            if (k == dir) vd = s.v[k];
-        out[0][j] = vd - t;
-        out[1][j] = entropy<D>(a.gas, s);
-        out[K - 1][j] = vd + t;
-        // tangential components: slot 2 + (k < dir ? k : k - 1) for k != dir
+            for (int k = 0; k < K; ++k) uj[k] = u[c][k][j];
+            const State<D> s = make_state<D>(a.gas, uj);
+            const double t = a.gas.two_inv_g1 * sound_speed<D>(a.gas, s);
+            double vd = s.v[0];
 #pragma unroll
-        for (int slot = 0; slot < D - 1; ++slot) {
-            double vt = 0.0;
+            for (int k = 1; k < D; ++k)
+                if (k == dir) vd = s.v[k];
+            out[0][j] = vd - t;
+            out[1][j] = entropy<D>(a.gas, s);
+            out[K - 1][j] = vd + t;
+            // tangential components: slot 2 + (k < dir ? k : k - 1) for k != dir
 #pragma unroll
-            for (int k = 0; k < D; ++k)
-                if (k != dir && (k < dir ? k : k - 1) == slot) vt = s.v[k];
-            out[2 + slot][j] = vt;
+            for (int slot = 0; slot < D - 1; ++slot) {
+                double vt = 0.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    if (k != dir && (k < dir ? k : k - 1) == slot) vt = s.v[k];
+                out[2 + slot][j] = vt;
+            }
         }
-    }
 #pragma unroll
-    for (int k = 0; k < K; ++k) L.store(a.out0, a.ld_out0, k, out[k]);
+        for (int k = 0; k < K; ++k) L.store(a.out0, a.ld_out0, k, c, out[k]);
+    }
 }
 
 template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void tile_char2cons(const Args &a, int64_t tile0)
 {
     constexpr int K = D + 2;
-    Lane<T, P, NT> L(a, tile0);
-    if (L.cnt == 0) return;
-    double w[K][P];
-    L.template load<K>(a.in0, a.ld_in0, w);
-    double out[K][P];
+    using L_t = Lane<T, P, NT>;
+    constexpr int W = L_t::W, NC = L_t::NC;
+    const L_t L(a, tile0);
+    if (!L.any()) return;
+    double w[NC][K][W];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) L.template load_fields<K>(a.in0, a.ld_in0, c, w[c]);
     const int dir = a.dir;
     const Gas &g = a.gas;
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-        const double wm = w[0][j], s = w[1][j], wp = w[K - 1][j];
-        const double c = g.quarter_g1 * (wp - wm);
-        const double c2 = c * c;
-        // rho = (c^2 / (gamma s))^(1/(gamma-1)),  p = rho c^2 / gamma
-        const double rho = pow(c2 * g.inv_gamma / s, g.inv_g1);
-        const double p = rho * c2 * g.inv_gamma;
-        double vp[K];
-        vp[0] = rho;
-        vp[K - 1] = p;
+    for (int c = 0; c < NC; ++c) {
+        double out[K][W];
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            double vk = 0.5 * (wp + wm);
-            if (k != dir) vk = w[2 + (k < dir ? k : k - 1)][j];
-            vp[1 + k] = vk;
+        for (int j = 0; j < W; ++j) {
+            const double wm = w[c][0][j], s = w[c][1][j], wp = w[c][K - 1][j];
+            const double cs = g.quarter_g1 * (wp - wm);
+            const double c2 = cs * cs;
+            // rho = (c^2 / (gamma s))^(1/(gamma-1)),  p = rho c^2 / gamma
+            const double rho = pow(c2 * g.inv_gamma / s, g.inv_g1);
+            const double p = rho * c2 * g.inv_gamma;
+            double vp[K];
+            vp[0] = rho;
+            vp[K - 1] = p;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                double vk = 0.5 * (wp + wm);
+                if (k != dir) vk = w[c][2 + (k < dir ? k : k - 1)][j];
+                vp[1 + k] = vk;
+            }
+            double uj[K];
+            from_primitive<D>(g, vp, uj);
+#pragma unroll
+            for (int k = 0; k < K; ++k) out[k][j] = uj[k];
         }
-        double uj[K];
-        from_primitive<D>(g, vp, uj);
 #pragma unroll
-        for (int k = 0; k < K; ++k) out[k][j] = uj[k];
+        for (int k = 0; k < K; ++k) L.store(a.out0, a.ld_out0, k, c, out[k]);
     }
-#pragma unroll
-    for (int k = 0; k < K; ++k) L.store(a.out0, a.ld_out0, k, out[k]);
 }
 
-// Ubar = sum_d A_d^T Fbar_d (dir < 0) or A_dir^T Fbar (dir >= 0).
+// Ubar = sum_d A_d^T Fbar_d (dir < 0) or A_dir^T Fbar (dir >= 0), chunk by
+// chunk: the state, the cotangents and the accumulators of W points.
 template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void tile_adjoint(const Args &a, int64_t tile0)
 {
     constexpr int K = D + 2;
-    Lane<T, P, NT> L(a, tile0);
-    if (L.cnt == 0) return;
-    double u[K][P];
-    L.template load<K>(a.in0, a.ld_in0, u);
-    State<D> s[P];
-    double phi[P], H[P];
-    double ub[K][P];
+    using L_t = Lane<T, P, NT>;
+    constexpr int W = L_t::W, NC = L_t::NC;
+    const L_t L(a, tile0);
+    if (!L.any()) return;
+    double u[NC][K][W];
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-        double uj[K];
+    for (int c = 0; c < NC; ++c) L.template load_fields<K>(a.in0, a.ld_in0, c, u[c]);
 #pragma unroll
-        for (int k = 0; k < K; ++k) uj[k] = u[k][j];
-        s[j] = make_state<D>(a.gas, uj);
-        phi[j] = a.gas.half_g1 * s[j].q;
-        H[j] = (s[j].E + s[j].p) * s[j].rinv;
+    for (int c = 0; c < NC; ++c) {
+        State<D> s[W];
+        double phi[W], H[W], ub[K][W];
 #pragma unroll
-        for (int k = 0; k < K; ++k) ub[k][j] = 0.0;
-    }
-    const T *fb = static_cast<const T *>(a.in1);
-    if (a.dir < 0) {
+        for (int j = 0; j < W; ++j) {
+            double uj[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) uj[k] = u[c][k][j];
+            s[j] = make_state<D>(a.gas, uj);
+            phi[j] = a.gas.half_g1 * s[j].q;
+            H[j] = (s[j].E + s[j].p) * s[j].rinv;
+#pragma unroll
+            for (int k = 0; k < K; ++k) ub[k][j] = 0.0;
+        }
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            double f[K][P];
+            if (a.dir >= 0 && d != a.dir) continue;
+            double f[K][W];
 #pragma unroll
-            for (int r = 0; r < K; ++r)
-                load_run<T, P>(fb + L.i + (int64_t)(r * D + d) * a.ld_in1, L.cnt, L.vec, f[r]);
+            for (int r = 0; r < K; ++r) L.load(a.in1, a.ld_in1, a.dir < 0 ? r * D + d : r, c, f[r]);
 #pragma unroll
-            for (int j = 0; j < P; ++j) {
+            for (int j = 0; j < W; ++j) {
                 double fj[K], uj[K];
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
@@ -398,40 +481,12 @@ __device__ __forceinline__ void tile_adjoint(const Args &a, int64_t tile0)
                 for (int k = 0; k < K; ++k) ub[k][j] = uj[k];
             }
         }
-    } else {
-        double f[K][P];
 #pragma unroll
-        for (int r = 0; r < K; ++r)
-            load_run<T, P>(fb + L.i + (int64_t)r * a.ld_in1, L.cnt, L.vec, f[r]);
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            if (d != a.dir) continue;
-#pragma unroll
-            for (int j = 0; j < P; ++j) {
-                double fj[K], uj[K];
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    fj[k] = f[k][j];
-                    uj[k] = ub[k][j];
-                }
-                adjoint_accumulate<D>(a.gas, s[j], phi[j], H[j], d, fj, uj);
-#pragma unroll
-                for (int k = 0; k < K; ++k) ub[k][j] = uj[k];
-            }
-        }
+        for (int k = 0; k < K; ++k) L.store(a.out0, a.ld_out0, k, c, ub[k]);
     }
-#pragma unroll
-    for (int k = 0; k < K; ++k) L.store(a.out0, a.ld_out0, k, ub[k]);
 }
 
 // ------------------------------------------------------------ Jacobian blocks
-
-// LDS bytes the Jacobian staging needs per workgroup of `block` threads.
-template <int D, typename T, int P>
-constexpr size_t jacobian_lds_bytes(int block)
-{
-    return (size_t)block * P * (D + 2) * (D + 2) * sizeof(T);
-}
 
 // Copy the wave's staged blocks (count elements of T, contiguous in LDS and
 // in global memory) with lane-contiguous 16-byte stores when allowed.
@@ -452,54 +507,50 @@ __device__ __forceinline__ void wave_copy_out(const T *lds, T *dst, int count, b
 
 // The fused pass: flux tensor (out0, may be NULL), Jacobian blocks (out1,
 // may be NULL) and Riemann invariants (out2, may be NULL) of the same state.
-// `lds` is this workgroup's staging area of jacobian_lds_bytes(blockDim.x);
-// every thread of the workgroup must call this (it holds barriers).
+// Flux and invariants are stored chunk by chunk from the full state; the
+// Jacobian keeps only v, H and phi of each point, and its blocks go through
+// `lds`, this workgroup's staging area of blockDim.x * P * K * K values
+// (each wave uses its own 64 * P blocks).  Every thread of the workgroup
+// must call this (it holds barriers).
 template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void tile_fused(const Args &a, int64_t tile0, T *lds)
 {
     constexpr int K = D + 2;
     constexpr int KK = K * K;
-    Lane<T, P, NT> L(a, tile0);
-    const int lane = threadIdx.x & (kWave - 1);
+    using L_t = Lane<T, P, NT>;
+    constexpr int W = L_t::W, NC = L_t::NC;
+    const L_t L(a, tile0);
     const int wave = threadIdx.x / kWave;
     const int64_t wave0 = tile0 + (int64_t)wave * kWave * P;
 
-    double u[K][P];
-    L.template load<K>(a.in0, a.ld_in0, u);
-    State<D> s[P];
+    double u[NC][K][W];
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-        double uj[K];
+    for (int c = 0; c < NC; ++c) L.template load_fields<K>(a.in0, a.ld_in0, c, u[c]);
+
+    double jv[P][D], jH[P], jphi[P];  // what the Jacobian blocks need
 #pragma unroll
-        for (int k = 0; k < K; ++k) uj[k] = u[k][j];
-        s[j] = make_state<D>(a.gas, uj);
+    for (int c = 0; c < NC; ++c) {
+        State<D> s[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            double uj[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) uj[k] = u[c][k][j];
+            s[j] = make_state<D>(a.gas, uj);
+            const int q = c * W + j;
+#pragma unroll
+            for (int k = 0; k < D; ++k) jv[q][k] = s[j].v[k];
+            jH[q] = (s[j].E + s[j].p) * s[j].rinv;
+            jphi[q] = a.gas.half_g1 * s[j].q;
+        }
+        if (L.any()) {
+            if (a.out0) store_flux<D, T, P, NT>(L, s, c, a.out0, a.ld_out0);
+            if (a.out2) store_riemann<D, T, P, NT>(a, L, s, c, a.out2, a.ld_out2);
+        }
+        __builtin_amdgcn_sched_barrier(0);  // one chunk's state at a time
     }
 
-    if (a.out0 && L.cnt > 0) {
-#pragma unroll
-        for (int r = 0; r < K; ++r) {
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                double f[P];
-#pragma unroll
-                for (int j = 0; j < P; ++j) f[j] = flux_entry<D>(s[j], r, d);
-                L.store(a.out0, a.ld_out0, r * D + d, f);
-            }
-        }
-    }
-    if (a.out2 && L.cnt > 0) {
-        double c[P];
-#pragma unroll
-        for (int j = 0; j < P; ++j) c[j] = sound_speed<D>(a.gas, s[j]);
-        store_riemann<D, T, P, NT>(a, L, s, c, a.out2, a.ld_out2);
-    }
     if (a.out1) {
-        double phi[P], H[P];
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-            phi[j] = a.gas.half_g1 * s[j].q;
-            H[j] = (s[j].E + s[j].p) * s[j].rinv;
-        }
         T *region = lds + (size_t)wave * kWave * P * KK;
         const int64_t left = a.n - wave0;
         const int wave_pts = left <= 0 ? 0 : (left >= kWave * P ? kWave * P : (int)left);
@@ -507,17 +558,20 @@ __device__ __forceinline__ void tile_fused(const Args &a, int64_t tile0, T *lds)
 #pragma unroll
         for (int d = 0; d < D; ++d) {
 #pragma unroll
-            for (int j = 0; j < P; ++j) {
-                T *blk = region + (lane * P + j) * KK;
+            for (int q = 0; q < P; ++q) {
+                T *blk = region + L.local(q) * KK;
 #pragma unroll
                 for (int r = 0; r < K; ++r)
 #pragma unroll
                     for (int c = 0; c < K; ++c)
-                        blk[r * K + c] = (T)jacobian_entry<D>(a.gas, s[j], phi[j], H[j], d, r, c);
+                        blk[r * K + c] = (T)jacobian_entry<D>(a.gas, jv[q], jphi[q], jH[q], d, r, c);
+                // one block at a time: keeps the scheduler from holding the
+                // entries of several blocks in registers at once
+                __builtin_amdgcn_sched_barrier(0);
             }
             __syncthreads();
             if (wave_pts > 0)
-                wave_copy_out<T, NT>(region, A + (d * a.ld_out1 + wave0) * KK, wave_pts * KK, L.vec, lane);
+                wave_copy_out<T, NT>(region, A + (d * a.ld_out1 + wave0) * KK, wave_pts * KK, L.vec, L.lane);
             __syncthreads();
         }
     }

@@ -513,6 +513,8 @@ int fdbb_set_launch_config(int op, int dim, int dtype, int block, int ppt, int g
     if (op < 0 || op >= FDBB_NUM_OPS || dim < 1 || dim > 3 || (dtype != FDBB_F64 && dtype != FDBB_F32))
         return fail(FDBB_EINVAL, "unknown op, dim or dtype");
     if (!config_ok(block, ppt, grid_cap, nontemporal)) return fail(FDBB_EINVAL, "invalid launch configuration");
+    if (family_of(op) == kFamFused && block > kMaxBlockStaged)
+        return fail(FDBB_EINVAL, "Jacobian kernels take at most 256 threads per workgroup");
     std::call_once(g_cfg_once, init_configs);
     Config c{block, ppt, grid_cap, nontemporal};
     g_cfg[op][dim - 1][dtype].store(pack(c));
@@ -528,6 +530,21 @@ int fdbb_get_launch_config(int op, int dim, int dtype, int *block, int *ppt, int
     if (ppt) *ppt = c.ppt;
     if (grid_cap) *grid_cap = c.grid_cap;
     if (nontemporal) *nontemporal = c.nt;
+    return FDBB_OK;
+}
+
+int fdbb_kernel_info(int op, int dim, int dtype, int ppt, int nontemporal, int *vgprs, int *scratch_bytes)
+{
+    if (op < 0 || op >= FDBB_NUM_OPS || dim < 1 || dim > 3 || (dtype != FDBB_F64 && dtype != FDBB_F32) ||
+        !(ppt == 1 || ppt == 2 || ppt == 4) || (nontemporal != 0 && nontemporal != 1))
+        return fail(FDBB_EINVAL, "unknown op, dim, dtype, ppt or store mode");
+    const void *fn = kernel_for(op, dim, dtype, ppt, nontemporal != 0);
+    if (!fn) return fail(FDBB_EINVAL, "no kernel for this configuration");
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(&attr, fn);
+    if (e != hipSuccess) return fail_hip(e, "hipFuncGetAttributes");
+    if (vgprs) *vgprs = attr.numRegs;
+    if (scratch_bytes) *scratch_bytes = (int)attr.localSizeBytes;
     return FDBB_OK;
 }
 
@@ -652,7 +669,9 @@ int stage_tasks(fdbb_batch_plan *p, const fdbb_task *tasks, int ntasks)
 
 int upload(fdbb_batch_plan *p, hipStream_t s)
 {
-    hipError_t e = hipMemcpyAsync(p->dev, p->host, p->bytes, hipMemcpyHostToDevice, s);
+    // header, prefix sums and the tasks in use (not the whole capacity)
+    const size_t used = (size_t)((unsigned char *)(p->tasks(p->host) + p->ntasks) - p->host);
+    hipError_t e = hipMemcpyAsync(p->dev, p->host, used, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync");
     e = hipEventRecord(p->uploaded, s);
     if (e != hipSuccess) return fail_hip(e, "hipEventRecord");
@@ -693,7 +712,8 @@ int fdbb_batch_plan_create(const fdbb_task *tasks, int ntasks, int capacity, int
     if (!plan) return fail(FDBB_EINVAL, "plan must not be NULL");
     *plan = nullptr;
     if (capacity < 1 || capacity < ntasks) return fail(FDBB_EINVAL, "capacity must be >= max(1, ntasks)");
-    if (!config_ok(block, ppt, grid, nontemporal)) return fail(FDBB_EINVAL, "invalid launch configuration");
+    if (!config_ok(block, ppt, grid, nontemporal) || block > kMaxBlockStaged)
+        return fail(FDBB_EINVAL, "invalid launch configuration (batches take at most 256 threads per workgroup)");
     if (ntasks > 0 && !tasks) return fail(FDBB_EINVAL, "tasks must not be NULL");
     // Argument checks of every task come before any HIP call.
     for (int b = 0; b < ntasks; ++b) {

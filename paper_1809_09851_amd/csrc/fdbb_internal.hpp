@@ -21,6 +21,12 @@ struct TaskDev {
     int32_t pad;
 };
 
+// Largest workgroup of the kernels that stage Jacobian blocks (the fused
+// kernel and the batch kernel).  Bounding them at 256 threads lets the
+// compiler give each thread up to 256 registers, so the staged blocks never
+// spill; their occupancy is set by LDS anyway.
+constexpr int kMaxBlockStaged = 256;
+
 // Kernel families (a family covers one or more public ops).
 enum Family : int {
     kFamCons2Prim = 0,

@@ -26,7 +26,7 @@ __device__ __forceinline__ void run_tile(int op, const Args &a, int64_t tile0, u
 }
 
 template <int P, bool NT>
-__global__ __launch_bounds__(1024) void k_batch(const TaskDev *__restrict__ tasks,
+__global__ __launch_bounds__(kMaxBlockStaged) void k_batch(const TaskDev *__restrict__ tasks,
                                                 const int64_t *__restrict__ prefix,
                                                 const int64_t *__restrict__ header)
 {

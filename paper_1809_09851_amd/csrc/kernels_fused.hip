@@ -6,7 +6,7 @@
 namespace fdbb {
 
 template <int D, typename T, int P, bool NT>
-__global__ __launch_bounds__(1024) void k_fused(Args a, int64_t ntiles)
+__global__ __launch_bounds__(kMaxBlockStaged) void k_fused(Args a, int64_t ntiles)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     T *lds = reinterpret_cast<T *>(smem);

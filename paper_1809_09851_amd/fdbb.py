@@ -75,6 +75,7 @@ def library():
         lib.fdbb_set_launch_config.argtypes = [_i, _i, _i, _i, _i, _i, _i]
         lib.fdbb_get_launch_config.argtypes = [_i, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i),
                                                ctypes.POINTER(_i), ctypes.POINTER(_i)]
+        lib.fdbb_kernel_info.argtypes = [_i, _i, _i, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]
         lib.fdbb_status_string.argtypes = [_i]
         lib.fdbb_status_string.restype = ctypes.c_char_p
         lib.fdbb_last_error.argtypes = []
@@ -267,6 +268,14 @@ def fdbb_get_launch_config(op, dim, dtype):
     check(library().fdbb_get_launch_config(op, dim, dtype, ctypes.byref(b), ctypes.byref(p),
                                            ctypes.byref(g), ctypes.byref(t)))
     return b.value, p.value, g.value, t.value
+
+
+def fdbb_kernel_info(op, dim, dtype, ppt, nontemporal=1):
+    """(vector registers, private spill bytes) per thread of a kernel."""
+    op = OPS[op] if isinstance(op, str) else op
+    v, b = _i(), _i()
+    check(library().fdbb_kernel_info(op, dim, dtype, ppt, nontemporal, ctypes.byref(v), ctypes.byref(b)))
+    return v.value, b.value
 
 
 def fdbb_version() -> int:

@@ -193,6 +193,19 @@ class Server:
 
 
 # -------------------------------------------------------------------- GPU
+def allocate_output(r: Request, stream):
+    """The request's output tensor, allocated in `stream`'s memory pool."""
+    import torch
+
+    from . import fdbb as F
+    dtype = torch.float64 if r.elem == 8 else torch.float32
+    kind, count = out_shape(r.op, r.dim, r.n)
+    with torch.cuda.stream(stream):
+        if kind == "fields":
+            return F.empty_fields(count, r.n, dtype)
+        return F.empty_blocks(r.dim, r.n, dtype)
+
+
 class GpuBatchExecutor:
     """One batch plan and one stream per slot; a launch packs all of its
     requests into the plan's task table and replays the plan's graph."""
@@ -209,14 +222,7 @@ class GpuBatchExecutor:
         self.events = [None] * slots
 
     def allocate(self, r: Request, stream):
-        from . import fdbb as F
-        torch = self.torch
-        dtype = torch.float64 if r.elem == 8 else torch.float32
-        kind, count = out_shape(r.op, r.dim, r.n)
-        with torch.cuda.stream(stream):
-            if kind == "fields":
-                return F.empty_fields(count, r.n, dtype)
-            return F.empty_blocks(r.dim, r.n, dtype)
+        return allocate_output(r, stream)
 
     def task(self, r: Request):
         B = self.B
@@ -232,9 +238,14 @@ class GpuBatchExecutor:
         s = self.streams[slot]
         for r in batch:
             r.out = self.allocate(r, s)
-        plan = self.plans[slot]
-        plan.update([self.task(r) for r in batch], stream=s)
-        plan.run(stream=s, graph=True)
+        if len(batch) == 1:
+            # a lone request gains nothing from the task table: launch it
+            # directly (same per-point code, so the same result bits)
+            single_launch(batch[0], s)
+        else:
+            plan = self.plans[slot]
+            plan.update([self.task(r) for r in batch], stream=s)
+            plan.run(stream=s, graph=True)
         ev = self.torch.cuda.Event()
         ev.record(s)
         self.events[slot] = ev
@@ -245,6 +256,20 @@ class GpuBatchExecutor:
     def close(self):
         for p in self.plans:
             p.close()
+
+
+def single_launch(r: Request, stream):
+    """Run one request through its single-call entry point on `stream`
+    (outputs already allocated in r.out)."""
+    from . import fdbb as F
+    if r.op == "cons2prim":
+        F.fdbb_cons2prim(r.dim, r.gamma, r.U, r.out, stream=stream)
+    elif r.op == "flux":
+        F.fdbb_flux(r.dim, r.gamma, r.U, r.out, stream=stream)
+    elif r.op == "flux_jacobian":
+        F.fdbb_flux_jacobian(r.dim, r.gamma, r.U, r.out, stream=stream)
+    else:
+        F.fdbb_flux_adjoint(r.dim, -1, r.gamma, r.U, r.Fbar, r.out, stream=stream)
 
 
 class SingleLaunchExecutor:
@@ -258,27 +283,14 @@ class SingleLaunchExecutor:
         self.events = {}
 
     def launch(self, slot: int, batch):
-        from . import fdbb as F
         torch = self.torch
         s = self.stream
         ev = None
         for r in batch:
-            dtype = torch.float64 if r.elem == 8 else torch.float32
-            with torch.cuda.stream(s):
-                if r.op == "cons2prim":
-                    r.out = F.empty_fields(r.dim + 2, r.n, dtype)
-                    F.fdbb_cons2prim(r.dim, r.gamma, r.U, r.out, stream=s)
-                elif r.op == "flux":
-                    r.out = F.empty_fields((r.dim + 2) * r.dim, r.n, dtype)
-                    F.fdbb_flux(r.dim, r.gamma, r.U, r.out, stream=s)
-                elif r.op == "flux_jacobian":
-                    r.out = F.empty_blocks(r.dim, r.n, dtype)
-                    F.fdbb_flux_jacobian(r.dim, r.gamma, r.U, r.out, stream=s)
-                else:
-                    r.out = F.empty_fields(r.dim + 2, r.n, dtype)
-                    F.fdbb_flux_adjoint(r.dim, -1, r.gamma, r.U, r.Fbar, r.out, stream=s)
-                ev = torch.cuda.Event()
-                ev.record(s)
+            r.out = allocate_output(r, s)
+            single_launch(r, s)
+            ev = torch.cuda.Event()
+            ev.record(s)
         self.events[slot] = ev
 
     def done(self, slot: int) -> bool:

@@ -28,7 +28,8 @@ BLOCKS = (64, 128, 256, 512, 1024)
 PPTS = (1, 2, 4)
 GRID_CAPS = (0, 2048, 4096, 8192)
 STORE_MODES = (1, 0)
-DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_gfx950.json")
+DEFAULT_TABLE = os.environ.get(
+    "FDBB_TUNED_TABLE", os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_gfx950.json"))
 DT = {"f64": (F.F64, torch.float64), "f32": (F.F32, torch.float32)}
 
 
@@ -120,6 +121,9 @@ def search(op: str, dim: int, dt: str, n: int, reps: int = 7, space=None, verbos
     old = F.fdbb_get_launch_config(op, dim, code)
     results = []
     for cfg in space:
+        # kernels that spill registers move extra bytes through HBM; skip them
+        if F.fdbb_kernel_info(op, dim, code, cfg[1], cfg[3])[1] > 0:
+            continue
         F.fdbb_set_launch_config(op, dim, code, *cfg)
         try:
             ms = time_launch(fn, reps)
@@ -156,7 +160,11 @@ def apply_table(path: str = DEFAULT_TABLE, key: str | None = None) -> int:
     for name, e in entries.items():
         op, dim, dt = name.split("/")
         code = DT[dt][0]
-        F.fdbb_set_launch_config(op, int(dim), code, e["block"], e["ppt"], e["grid_cap"], e["nt"])
+        try:
+            F.fdbb_set_launch_config(op, int(dim), code, e["block"], e["ppt"], e["grid_cap"], e["nt"])
+        except F.FdbbError as exc:  # an entry the library no longer accepts keeps the default
+            print(f"fdbb: ignoring tuned entry {name}: {exc}", file=sys.stderr)
+            continue
         count += 1
     return count
 

@@ -122,6 +122,13 @@ def test_launch_config_table():
     assert F.fdbb_get_launch_config("flux", 3, 0) == old
 
 
+def test_kernel_info_rejects_bad_arguments():
+    lib = F.library()
+    assert lib.fdbb_kernel_info(3, 3, 0, 3, 1, None, None) == F.EINVAL
+    assert lib.fdbb_kernel_info(3, 0, 0, 1, 1, None, None) == F.EINVAL
+    assert lib.fdbb_kernel_info(3, 3, 0, 1, 2, None, None) == F.EINVAL
+
+
 def test_batch_plan_rejects_bad_tasks():
     lib = F.library()
     plan = ctypes.c_void_p()

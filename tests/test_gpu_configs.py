@@ -38,7 +38,7 @@ def test_fused_all_configs(block, ppt, grid, nt):
                 Fg, A, R = _with_config("fused", dim, code, (block, ppt, grid, nt),
                                         lambda: F.euler_fused(Ug, GAMMA))
             except F.FdbbError as e:
-                assert e.status == F.EINVAL and lds > 65536, (dt, dim, str(e))
+                assert e.status == F.EINVAL and (lds > 65536 or block > 256), (dt, dim, str(e))
                 continue
             Fo, Ao, Ro = oracle.fused(dim, GAMMA, Uo)
             assert group_error(host(Fg), Fo, flux_groups(dim)) <= TOL[dt]
@@ -56,7 +56,11 @@ def test_pointwise_all_configs(block, ppt, grid, nt):
         assert group_error(host(Fg), oracle.flux(dim, GAMMA, Uo), flux_groups(dim)) <= TOL[dt]
         V = _with_config("cons2prim", dim, code, (block, ppt, grid, nt), lambda: F.cons2prim(Ug, GAMMA))
         assert group_error(host(V), oracle.cons2prim(dim, GAMMA, Uo), state_groups(dim)) <= TOL[dt]
-        A = _with_config("flux_jacobian", dim, code, (block, ppt, grid, nt), lambda: _try_jac(Ug))
+        try:
+            A = _with_config("flux_jacobian", dim, code, (block, ppt, grid, nt), lambda: _try_jac(Ug))
+        except F.FdbbError as e:
+            assert e.status == F.EINVAL and block > 256
+            A = None
         if A is not None:
             assert blocks_error(host(A), oracle.flux_jacobian(dim, GAMMA, Uo)) <= TOL[dt]
 

@@ -60,7 +60,13 @@ def test_alone_equals_mix_and_oracle(pools):
         s1 = S.Server(ex1, 200 * 10 ** 9, slots=1)
         (alone,) = s1.run_arrivals([pools.request(s)])
         torch.cuda.synchronize()
-        assert torch.equal(alone.out, by_id[k].out), f"request {k} ({s['op']}) differs alone vs mix"
+        # alone, a request runs through its single-call kernel; in the mix,
+        # through the batch kernel: same per-point code, so equal up to the
+        # compiler's contractions, well inside the stated tolerance
+        a_out, m_out = host(alone.out), host(by_id[k].out)
+        tol = 1e-14 if alone.elem == 8 else 1.2e-7
+        den = np.maximum(np.abs(m_out).max(axis=0, keepdims=True), 1e-300)
+        assert np.max(np.abs(a_out - m_out) / den) <= tol, f"request {k} ({s['op']}) alone vs mix"
         ex1.close()
     for r in mixed:
         _check_oracle(r)
