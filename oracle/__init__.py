@@ -12,6 +12,7 @@ arithmetic.  Every function takes and returns SoA arrays of shape
 
 Sections cited below are those of the FDBB paper:
   * cons2prim / prim2cons       -- Sec. 2.2, "Variables" (conversion figure)
+  * v_mag2                      -- Sec. 3, Eq. 2 (micro-benchmark expression)
   * eos                         -- Sec. 2.2, "Equations of state" (p_rhoe)
   * flux                        -- Sec. 2.2, "Inviscid Fluxes" (flux tensor)
   * flux_jacobian               -- Fig. 1 / Sec. 2.2 (derivative of the above)
@@ -78,6 +79,8 @@ class Oracle:
                      "oracle_flux_jacobian", "oracle_riemann_invariants"):
             getattr(lib, name).argtypes = sig
             getattr(lib, name).restype = _int
+        lib.oracle_v_mag2.argtypes = [_int, _dp, _i64, _dp, _i64]
+        lib.oracle_v_mag2.restype = _int
         lib.oracle_eos.argtypes = [_int, _dbl, _dp, _i64, _dp, _dp, _i64]
         lib.oracle_eos.restype = _int
         for name in ("oracle_cons2char", "oracle_char2cons"):
@@ -102,6 +105,14 @@ class Oracle:
         U = np.empty_like(V)
         _check(self.lib.oracle_prim2cons(dim, gamma, _ptr(V), n, _ptr(U), n, n))
         return U
+
+    def v_mag2(self, dim, U):
+        """|v|^2 of each point, shape (n,)."""
+        U = _soa(U, dim + 2)
+        n = U.shape[1]
+        y = np.empty(n)
+        _check(self.lib.oracle_v_mag2(dim, _ptr(U), n, _ptr(y), n))
+        return y
 
     def eos(self, dim, gamma, U):
         """Returns (p, c), each of shape (n,)."""
@@ -195,6 +206,10 @@ def prim2cons(dim, gamma, V):
 
 def eos(dim, gamma, U):
     return default().eos(dim, gamma, U)
+
+
+def v_mag2(dim, U):
+    return default().v_mag2(dim, U)
 
 
 def flux(dim, gamma, U):

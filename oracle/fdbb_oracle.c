@@ -112,6 +112,26 @@ int oracle_prim2cons(int dim, double gamma, const double *V, int64_t ldV,
     return 0;
 }
 
+/* Squared velocity magnitude from the conservative state, the paper's
+ * micro-benchmark expression (Sec. 3, Eq. 2): |v|^2 = (m . m) / (rho rho). */
+int oracle_v_mag2(int dim, const double *U, int64_t ldU, double *y, int64_t n)
+{
+    int64_t i;
+    int k;
+    if (!dim_ok(dim))
+        return -1;
+    for (i = 0; i < n; ++i) {
+        double rho = U[0 * ldU + i];
+        double mm = 0.0;
+        for (k = 0; k < dim; ++k) {
+            double m = U[(1 + k) * ldU + i];
+            mm = mm + m * m;
+        }
+        y[i] = mm / (rho * rho);
+    }
+    return 0;
+}
+
 /* Equation of state of the perfect gas (Sec. 2.2, "Equations of state"):
  * pressure p and speed of sound c = sqrt(gamma p / rho).  Either output
  * may be NULL. */

@@ -127,6 +127,26 @@ def pin_temperature_route(o):
                       "energy flux = mass flux * total enthalpy")
 
 
+def pin_v_mag2(o):
+    """|v|^2 of the temperature-route states (v known), a worked value, and
+    frame indifference (rotation) and a Galilean boost."""
+    for dim in (1, 2, 3):
+        U, rho, v, T = thermal_state(dim, 64, 15 + dim, 1.4)
+        close(o.v_mag2(dim, U), (v * v).sum(axis=0), 1e-14, "v_mag2 = |v|^2")
+    U = np.array([[2.0], [2.0], [4.0], [4.0], [50.0]])
+    close(o.v_mag2(3, U), [9.0], 1e-15, "v_mag2 worked value (4 + 16 + 16) / 4")
+    rng = np.random.default_rng(17)
+    U, rho, v, T = thermal_state(3, 32, 18, 1.4)
+    Q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    UQ = U.copy()
+    UQ[1:4] = Q @ U[1:4]
+    close(o.v_mag2(3, UQ), o.v_mag2(3, U), 1e-14, "v_mag2 rotation")
+    w = rng.normal(size=(3, 1))
+    Ub = U.copy()
+    Ub[1:4] = U[1:4] + rho * w
+    close(o.v_mag2(3, Ub), ((v + w) ** 2).sum(axis=0), 1e-13, "v_mag2 boost")
+
+
 def pin_roundtrip(o):
     for dim in (1, 2, 3):
         for g in GAMMAS:
@@ -454,6 +474,7 @@ def pin_adjoint_fd(o):
 
 PINS = [
     pin_worked_state,
+    pin_v_mag2,
     pin_temperature_route,
     pin_roundtrip,
     pin_galilean,

@@ -39,6 +39,8 @@ MUTATIONS = [
     ("char2cons sound speed", "c = 0.25 * g1 * (wp - wm);", "c = 0.5 * g1 * (wp - wm);"),
     ("cons2char tangential", "W[slot * ldW + i] = s.v[j];", "W[slot * ldW + i] = s.v[dir];"),
     ("cons2char entropy", "W[1 * ldW + i] = s.p / pow(s.rho, gamma);", "W[1 * ldW + i] = s.p;"),
+    ("v_mag2 divides by rho once", "y[i] = mm / (rho * rho);", "y[i] = mm / rho;"),
+    ("v_mag2 drops a component", "for (k = 0; k < dim; ++k) {\n            double m", "for (k = 1; k < dim; ++k) {\n            double m"),
     ("adjoint not transposed", "acc[c] = acc[c] + blk[r][c] * Fb[field * ldFb + i];",
      "acc[c] = acc[c] + blk[c][r] * Fb[field * ldFb + i];"),
     ("adjoint cotangent layout", "int64_t field = (dir >= 0) ? r : (r * dim + d);",
