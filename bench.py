@@ -332,6 +332,35 @@ def bench_batched(steps: int, warmup: int, dtype, nblocks: int = 512):
     return res
 
 
+def bench_paper_sweeps(steps: int = 20, warmup: int = 3, lo: int = 10, hi: int = 28):
+    """The paper's two experiments on this GPU, over N = 2^lo..2^hi:
+    the micro-benchmark expression |v|^2 = (m.m)/(rho rho) of Sec. 3, Eq. 2
+    (3D, FP32 storage as in the paper; 20 B and 7 flops per point), and the
+    mini-application's repeated evaluation of the 3D inviscid flux tensor
+    (FP32 storage, 80 B per point), as time per evaluation."""
+    import torch
+    from paper_1809_09851_amd import fdbb as F
+    from paper_1809_09851_amd import tune
+    rows = []
+    for e in range(lo, hi + 1):
+        n = 1 << e
+        U = tune._state(3, n, torch.float32)
+        y = torch.empty(n, dtype=torch.float32, device="cuda")
+        Fo = F.empty_fields(15, n, torch.float32)
+        _, ev_v = timed_launches(lambda: F.fdbb_velocity_magnitude2(3, U, y), steps, warmup)
+        _, ev_f = timed_launches(lambda: F.fdbb_flux(3, GAMMA, U, Fo), steps, warmup)
+        rows.append({"n": n, "vmag2_us": round(ev_v * 1e3, 2),
+                     "vmag2_gbs": round(20 * n / (ev_v * 1e-3) / 1e9, 1),
+                     "vmag2_gflops": round(7 * n / (ev_v * 1e-3) / 1e9, 1),
+                     "flux_us": round(ev_f * 1e3, 2),
+                     "flux_gbs": round(80 * n / (ev_f * 1e-3) / 1e9, 1)})
+        print(f"# sweep n=2^{e}: v_mag2 {rows[-1]['vmag2_us']} us, flux {rows[-1]['flux_us']} us",
+              file=sys.stderr, flush=True)
+        del U, y, Fo
+        torch.cuda.empty_cache()
+    return rows
+
+
 def bench_probes(steps: int, warmup: int, gib: float = 4.0):
     """What HBM delivers to plain streaming kernels: read, write, copy."""
     import torch
@@ -363,6 +392,8 @@ def main(argv=None):
                     help="comma-separated Poisson rates (req/s) for the serving measurement; '' skips it")
     ap.add_argument("--serve-count", type=int, default=1000)
     ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--paper-sweeps", action="store_true",
+                    help="also run the paper's micro-benchmark and mini-application sweeps (N = 2^10..2^28)")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run the 1 GiB copy probe 3 times (hardware byte-counter calibration)")
     args = ap.parse_args(argv)
@@ -421,6 +452,8 @@ def main(argv=None):
         ex["batched_512_f32"] = bench_batched(5, 2, torch.float32)
         ex["hbm_probes_gbs"] = bench_probes(max(10, args.steps // 5), 3)
         line["extras"] = ex
+    if args.paper_sweeps:
+        line["paper_sweeps"] = bench_paper_sweeps()
     rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
     if rates:
         line["serving"] = bench_serving(rates, args.serve_count, args.serve_warmup)

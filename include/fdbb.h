@@ -82,7 +82,8 @@ typedef enum {
     FDBB_OP_CHAR2CONS = 7,
     FDBB_OP_FUSED = 8,
     FDBB_OP_ADJOINT = 9,
-    FDBB_NUM_OPS = 10
+    FDBB_OP_V_MAG2 = 10,
+    FDBB_NUM_OPS = 11
 } fdbb_op;
 
 /* Conservative -> primitive (Sec. 2.2, "Variables", conversion figure):
@@ -95,6 +96,12 @@ int fdbb_cons2prim(int dim, double gamma, int dtype, const void *U, int64_t ldU,
  * U = (rho, rho v, p / (gamma-1) + rho |v|^2 / 2).  U == V converts in place. */
 int fdbb_prim2cons(int dim, double gamma, int dtype, const void *V, int64_t ldV,
                    void *U, int64_t ldU, int64_t n, void *stream);
+
+/* Squared velocity magnitude, the expression of the paper's micro-benchmark
+ * (Sec. 3, Eq. 2): y[i] = (m . m) / (rho rho).  Reads rho and m (fields
+ * 0..D of U; E is not touched) and writes one field of n elements. */
+int fdbb_velocity_magnitude2(int dim, int dtype, const void *U, int64_t ldU, void *y, int64_t n,
+                             void *stream);
 
 /* Equation of state of the perfect gas (Sec. 2.2, "Equations of state";
  * the pressure is the p_rhoe member of the EOS prototype, p = (gamma-1) rho e):
@@ -177,7 +184,7 @@ int fdbb_kernel_info(int op, int dim, int dtype, int ppt, int nontemporal, int *
  * names one operation on one field-set group; its fields mean what the
  * matching single-call entry point's arguments mean:
  *   in0  = U (V for prim2cons, W for char2cons), in1 = Fbar (adjoint only),
- *   out0 = V / U / p / F / A / R / W / Ubar, out1 = c (eos) or A (fused),
+ *   out0 = V / U / p / F / A / R / W / Ubar / y (v_mag2), out1 = c (eos) or A (fused),
  *   out2 = R (fused).  Unused pointers are NULL. */
 typedef struct {
     int32_t op;     /* fdbb_op */

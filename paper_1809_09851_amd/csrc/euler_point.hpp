@@ -87,6 +87,16 @@ __device__ __forceinline__ void from_primitive(const Gas &g, const double *vp, d
     out[D + 1] = vp[D + 1] * g.inv_g1 + 0.5 * rho * q;
 }
 
+// (m . m) / (rho rho), in the order the micro-benchmark expression writes it.
+template <int D>
+__device__ __forceinline__ double velocity_magnitude2(const double *u)
+{
+    double mm = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) mm += u[1 + k] * u[1 + k];
+    return mm / (u[0] * u[0]);
+}
+
 // Component r of the inviscid flux in direction d: F_d = (m_d,
 // m_i v_d + delta_id p, v_d (E + p)).
 template <int D>

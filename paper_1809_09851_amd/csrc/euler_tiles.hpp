@@ -225,6 +225,31 @@ __device__ __forceinline__ void tile_prim2cons(const Args &a, int64_t tile0)
 }
 
 template <int D, typename T, int P, bool NT>
+__device__ __forceinline__ void tile_vmag2(const Args &a, int64_t tile0)
+{
+    constexpr int R = D + 1;  // rho and the momenta; E is not read
+    using L_t = Lane<T, P, NT>;
+    constexpr int W = L_t::W, NC = L_t::NC;
+    const L_t L(a, tile0);
+    if (!L.any()) return;
+    double u[NC][R][W];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) L.template load_fields<R>(a.in0, a.ld_in0, c, u[c]);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double y[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            double uj[R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) uj[k] = u[c][k][j];
+            y[j] = velocity_magnitude2<D>(uj);
+        }
+        L.store(a.out0, 0, 0, c, y);
+    }
+}
+
+template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void tile_eos(const Args &a, int64_t tile0)
 {
     constexpr int K = D + 2;

@@ -236,6 +236,7 @@ int family_of(int op)
     case FDBB_OP_FLUX_JACOBIAN:
     case FDBB_OP_FUSED: return kFamFused;
     case FDBB_OP_ADJOINT: return kFamAdjoint;
+    case FDBB_OP_V_MAG2: return kFamVmag2;
     default: return -1;
     }
 }
@@ -248,7 +249,8 @@ const void *kernel_for(int op, int dim, int dtype, int ppt, bool nt)
     case kFamPrim2Cons:
     case kFamEos:
     case kFamFlux:
-    case kFamRiemann: return kernel_pointwise(fam, dim, dtype, ppt, nt);
+    case kFamRiemann:
+    case kFamVmag2: return kernel_pointwise(fam, dim, dtype, ppt, nt);
     case kFamCons2Char:
     case kFamChar2Cons: return kernel_char(fam, dim, dtype, ppt, nt);
     case kFamFused: return kernel_fused(dim, dtype, ppt, nt);
@@ -359,6 +361,11 @@ int build_call(Call &c, const fdbb_task &t)
         if ((rc = add_fields(c, t.in0, t.ld_in0, K, 1, true, true, "U"))) return rc;
         if ((rc = add_fields(c, t.out0, t.ld_out0, (int64_t)K * D, 1, false, true, "F"))) return rc;
         break;
+    case FDBB_OP_V_MAG2:
+        a.in0 = t.in0, a.ld_in0 = t.ld_in0, a.out0 = t.out0;
+        if ((rc = add_fields(c, t.in0, t.ld_in0, D + 1, 1, true, true, "U"))) return rc;
+        if ((rc = add_fields(c, t.out0, 0, 1, 1, false, true, "y"))) return rc;
+        break;
     case FDBB_OP_RIEMANN:
         a.in0 = t.in0, a.ld_in0 = t.ld_in0, a.out0 = t.out0, a.ld_out0 = t.ld_out0;
         if ((rc = add_fields(c, t.in0, t.ld_in0, K, 1, true, true, "U"))) return rc;
@@ -438,6 +445,14 @@ int fdbb_prim2cons(int dim, double gamma, int dtype, const void *V, int64_t ldV,
 {
     fdbb_task t = make_task(FDBB_OP_PRIM2CONS, dim, 0, gamma, dtype, n);
     t.in0 = V, t.ld_in0 = ldV, t.out0 = U, t.ld_out0 = ldU;
+    return run(t, stream);
+}
+
+int fdbb_velocity_magnitude2(int dim, int dtype, const void *U, int64_t ldU, void *y, int64_t n, void *stream)
+{
+    // gamma does not enter |v|^2; any valid value passes validation
+    fdbb_task t = make_task(FDBB_OP_V_MAG2, dim, 0, 1.4, dtype, n);
+    t.in0 = U, t.ld_in0 = ldU, t.out0 = y;
     return run(t, stream);
 }
 

@@ -38,6 +38,7 @@ enum Family : int {
     kFamChar2Cons,
     kFamFused,  // fused pass and flux Jacobian (F and R NULL)
     kFamAdjoint,
+    kFamVmag2,
     kNumFamilies
 };
 

@@ -21,6 +21,7 @@ __device__ __forceinline__ void run_tile(int op, const Args &a, int64_t tile0, u
     case 6: tile_cons2char<D, T, P, NT>(a, tile0); break;
     case 7: tile_char2cons<D, T, P, NT>(a, tile0); break;
     case 9: tile_adjoint<D, T, P, NT>(a, tile0); break;
+    case 10: tile_vmag2<D, T, P, NT>(a, tile0); break;
     default: break;
     }
 }

@@ -1,5 +1,5 @@
 // Single-operation kernels for the pointwise building blocks: cons2prim,
-// prim2cons, EOS, flux tensor and Riemann invariants.  Each workgroup loops
+// prim2cons, EOS, flux tensor, Riemann invariants and |v|^2.  Each workgroup loops
 // over tiles of blockDim.x * P points (grid-stride when the grid is capped).
 #include "fdbb_internal.hpp"
 
@@ -16,6 +16,7 @@ __global__ __launch_bounds__(1024) void k_pointwise(Args a, int64_t ntiles)
         else if constexpr (FAM == kFamEos) tile_eos<D, T, P, NT>(a, tile0);
         else if constexpr (FAM == kFamFlux) tile_flux<D, T, P, NT>(a, tile0);
         else if constexpr (FAM == kFamRiemann) tile_riemann<D, T, P, NT>(a, tile0);
+        else if constexpr (FAM == kFamVmag2) tile_vmag2<D, T, P, NT>(a, tile0);
     }
 }
 
@@ -59,6 +60,7 @@ const void *kernel_pointwise(int family, int dim, int dtype, int ppt, bool nt)
     case kFamEos: return pick<kFamEos>(dim, dtype, ppt, nt);
     case kFamFlux: return pick<kFamFlux>(dim, dtype, ppt, nt);
     case kFamRiemann: return pick<kFamRiemann>(dim, dtype, ppt, nt);
+    case kFamVmag2: return pick<kFamVmag2>(dim, dtype, ppt, nt);
     default: return nullptr;
     }
 }

