@@ -18,6 +18,8 @@ Sections cited below are those of the FDBB paper:
   * flux_jacobian               -- Fig. 1 / Sec. 2.2 (derivative of the above)
   * riemann_invariants, cons2char, char2cons -- Fig. 1 (named building blocks)
   * flux_adjoint                -- transpose of the flux Jacobians
+  * eigenvectors, char_apply    -- characteristic decomposition of A_d (Fig. 1,
+                                   "characteristic variables", linearised)
 """
 from __future__ import annotations
 
@@ -89,6 +91,10 @@ class Oracle:
         lib.oracle_flux_adjoint.argtypes = [_int, _int, _dbl, _dp, _i64, _dp, _i64,
                                             _dp, _i64, _i64]
         lib.oracle_flux_adjoint.restype = _int
+        lib.oracle_eigenvectors.argtypes = [_int, _dbl, _dp, _i64, _dp, _i64, _dp, _i64, _i64]
+        lib.oracle_eigenvectors.restype = _int
+        lib.oracle_char_apply.argtypes = [_int, _int, _int, _dbl, _dp, _i64, _dp, _i64, _dp, _i64, _i64]
+        lib.oracle_char_apply.restype = _int
         self.lib = lib
         self.path = path
 
@@ -177,6 +183,33 @@ class Oracle:
                                             _ptr(Fbar), n, _ptr(Ub), n, n))
         return Ub
 
+    def eigenvectors(self, dim, gamma, U):
+        """(L, R), each of shape (D, n, K, K): R_d holds the right
+        eigenvectors of A_d as columns, L_d = R_d^{-1}."""
+        U = _soa(U, dim + 2)
+        n = U.shape[1]
+        K = dim + 2
+        L = np.empty((dim, n, K, K))
+        R = np.empty((dim, n, K, K))
+        rc = self.lib.oracle_eigenvectors(dim, gamma, _ptr(U), n, _ptr(L), n, _ptr(R), n, n)
+        if rc == -2:
+            raise ValueError("singular eigenvector matrix")
+        _check(rc)
+        return L, R
+
+    def char_apply(self, dim, direction, mode, gamma, U, X):
+        """Y = L_dir X (mode 0) or R_dir X (mode 1), X and Y of shape (K, n)."""
+        K = dim + 2
+        U = _soa(U, K)
+        X = _soa(X, K)
+        n = U.shape[1]
+        Y = np.empty_like(U)
+        rc = self.lib.oracle_char_apply(dim, direction, mode, gamma, _ptr(U), n, _ptr(X), n, _ptr(Y), n, n)
+        if rc == -2:
+            raise ValueError("singular eigenvector matrix")
+        _check(rc)
+        return Y
+
     def fused(self, dim, gamma, U):
         """The fused pass is, by definition, the flux, the flux Jacobians and
         the Riemann invariants of the same state."""
@@ -238,3 +271,11 @@ def flux_adjoint(dim, direction, gamma, U, Fbar):
 
 def fused(dim, gamma, U):
     return default().fused(dim, gamma, U)
+
+
+def eigenvectors(dim, gamma, U):
+    return default().eigenvectors(dim, gamma, U)
+
+
+def char_apply(dim, direction, mode, gamma, U, X):
+    return default().char_apply(dim, direction, mode, gamma, U, X)

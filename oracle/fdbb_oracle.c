@@ -373,3 +373,148 @@ int oracle_flux_adjoint(int dim, int dir, double gamma, const double *U,
     }
     return 0;
 }
+
+/* Right eigenvectors of A_dir as the columns of a K x K matrix, in the order
+ * of the eigenvalues v_d - c, v_d (entropy, then the tangential directions
+ * in ascending order), v_d + c (the order of the characteristic variables
+ * above).  Normalised with a unit density component for the acoustic and
+ * entropy waves and a unit tangential momentum for the shear waves:
+ *   r- = (1, v - c e_d, H - c v_d),  r0 = (1, v, |v|^2/2),
+ *   r_j = (0, e_j, v_j) for j != d,   r+ = (1, v + c e_d, H + c v_d). */
+static void right_eigenvectors(int dim, double gamma, const point_state *s, int d,
+                               double Rm[ORACLE_MAXK][ORACLE_MAXK])
+{
+    int K = dim + 2, r, c, j, col;
+    double cs = sqrt(gamma * s->p / s->rho);
+    double H = (s->E + s->p) / s->rho;
+    for (r = 0; r < K; ++r)
+        for (c = 0; c < K; ++c)
+            Rm[r][c] = 0.0;
+    /* r- */
+    Rm[0][0] = 1.0;
+    for (j = 0; j < dim; ++j)
+        Rm[1 + j][0] = s->v[j] - (j == d ? cs : 0.0);
+    Rm[K - 1][0] = H - cs * s->v[d];
+    /* r0 */
+    Rm[0][1] = 1.0;
+    for (j = 0; j < dim; ++j)
+        Rm[1 + j][1] = s->v[j];
+    Rm[K - 1][1] = 0.5 * s->q;
+    /* shear waves */
+    col = 2;
+    for (j = 0; j < dim; ++j) {
+        if (j == d)
+            continue;
+        Rm[1 + j][col] = 1.0;
+        Rm[K - 1][col] = s->v[j];
+        col = col + 1;
+    }
+    /* r+ */
+    Rm[0][K - 1] = 1.0;
+    for (j = 0; j < dim; ++j)
+        Rm[1 + j][K - 1] = s->v[j] + (j == d ? cs : 0.0);
+    Rm[K - 1][K - 1] = H + cs * s->v[d];
+}
+
+/* Inverse of a K x K matrix by Gauss-Jordan elimination with partial
+ * pivoting.  Returns 0, or -1 for a singular matrix. */
+static int invert(int K, double M[ORACLE_MAXK][ORACLE_MAXK], double X[ORACLE_MAXK][ORACLE_MAXK])
+{
+    double a[ORACLE_MAXK][2 * ORACLE_MAXK];
+    int r, c, k, piv;
+    for (r = 0; r < K; ++r)
+        for (c = 0; c < 2 * K; ++c)
+            a[r][c] = (c < K) ? M[r][c] : (c - K == r ? 1.0 : 0.0);
+    for (k = 0; k < K; ++k) {
+        piv = k;
+        for (r = k + 1; r < K; ++r)
+            if (fabs(a[r][k]) > fabs(a[piv][k]))
+                piv = r;
+        if (a[piv][k] == 0.0)
+            return -1;
+        if (piv != k)
+            for (c = 0; c < 2 * K; ++c) {
+                double t = a[k][c];
+                a[k][c] = a[piv][c];
+                a[piv][c] = t;
+            }
+        {
+            double inv = 1.0 / a[k][k];
+            for (c = 0; c < 2 * K; ++c)
+                a[k][c] = a[k][c] * inv;
+        }
+        for (r = 0; r < K; ++r) {
+            double f;
+            if (r == k)
+                continue;
+            f = a[r][k];
+            for (c = 0; c < 2 * K; ++c)
+                a[r][c] = a[r][c] - f * a[k][c];
+        }
+    }
+    for (r = 0; r < K; ++r)
+        for (c = 0; c < K; ++c)
+            X[r][c] = a[r][K + c];
+    return 0;
+}
+
+/* Characteristic decomposition A_d = R_d diag(lambda) L_d of every
+ * direction: R_d as above and L_d = R_d^{-1}, both as point-major row-major
+ * K x K blocks (the Jacobian layout).  Either output may be NULL.  Returns -2
+ * if some R_d is singular (c = 0). */
+int oracle_eigenvectors(int dim, double gamma, const double *U, int64_t ldU,
+                        double *L, int64_t ldL, double *R, int64_t ldR, int64_t n)
+{
+    int64_t i;
+    int d, r, c, K = dim + 2;
+    double Rm[ORACLE_MAXK][ORACLE_MAXK], Lm[ORACLE_MAXK][ORACLE_MAXK];
+    if (!dim_ok(dim))
+        return -1;
+    for (i = 0; i < n; ++i) {
+        point_state s = load_cons(dim, gamma, U, ldU, i);
+        for (d = 0; d < dim; ++d) {
+            right_eigenvectors(dim, gamma, &s, d, Rm);
+            if (R)
+                for (r = 0; r < K; ++r)
+                    for (c = 0; c < K; ++c)
+                        R[(d * ldR + i) * (int64_t)(K * K) + r * K + c] = Rm[r][c];
+            if (L) {
+                if (invert(K, Rm, Lm) != 0)
+                    return -2;
+                for (r = 0; r < K; ++r)
+                    for (c = 0; c < K; ++c)
+                        L[(d * ldL + i) * (int64_t)(K * K) + r * K + c] = Lm[r][c];
+            }
+        }
+    }
+    return 0;
+}
+
+/* Y = L_dir(U) X (mode 0: state increments to characteristic increments)
+ * or Y = R_dir(U) X (mode 1: back), with X and Y K-field sets. */
+int oracle_char_apply(int dim, int dir, int mode, double gamma, const double *U, int64_t ldU,
+                      const double *X, int64_t ldX, double *Y, int64_t ldY, int64_t n)
+{
+    int64_t i;
+    int r, c, K = dim + 2;
+    double Rm[ORACLE_MAXK][ORACLE_MAXK], Lm[ORACLE_MAXK][ORACLE_MAXK];
+    if (!dim_ok(dim) || dir < 0 || dir >= dim || mode < 0 || mode > 1)
+        return -1;
+    for (i = 0; i < n; ++i) {
+        point_state s = load_cons(dim, gamma, U, ldU, i);
+        double (*M)[ORACLE_MAXK] = Rm;
+        right_eigenvectors(dim, gamma, &s, dir, Rm);
+        if (mode == 0) {
+            if (invert(K, Rm, Lm) != 0)
+                return -2;
+            M = Lm;
+        }
+        for (r = 0; r < K; ++r) {
+            double acc = 0.0;
+            for (c = 0; c < K; ++c)
+                acc = acc + M[r][c] * X[c * ldX + i];
+            Y[r * ldY + i] = acc;
+        }
+    }
+    return 0;
+}

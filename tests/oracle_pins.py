@@ -472,6 +472,37 @@ def pin_adjoint_fd(o):
         close(tot, Ub, 1e-13, "adjoint: all directions = sum of single directions")
 
 
+def pin_characteristic_decomposition(o):
+    """A_d R_d = R_d diag(v_d - c, v_d .., v_d + c) and L_d A_d = diag(..) L_d
+    against the (separately pinned) Jacobian; L_d R_d = I; char_apply is
+    the product with L_d or R_d."""
+    for dim in (1, 2, 3):
+        for g in GAMMAS:
+            U, rho, v, T = thermal_state(dim, 16, 170 + dim, g)
+            c = np.sqrt(g * T)
+            A = o.flux_jacobian(dim, g, U)
+            L, R = o.eigenvectors(dim, g, U)
+            K = dim + 2
+            for d in range(dim):
+                for i in range(U.shape[1]):
+                    lam = np.diag([v[d, i] - c[i]] + [v[d, i]] * dim + [v[d, i] + c[i]])
+                    scale = np.linalg.norm(A[d, i], np.inf) * np.linalg.norm(R[d, i], np.inf)
+                    close(A[d, i] @ R[d, i], R[d, i] @ lam, 1e-13, "A R = R Lambda", scale=scale)
+                    close(L[d, i] @ A[d, i], lam @ L[d, i], 1e-12, "L A = Lambda L",
+                          scale=np.linalg.norm(A[d, i], np.inf) * np.linalg.norm(L[d, i], np.inf))
+                    close(L[d, i] @ R[d, i], np.eye(K), 1e-13, "L R = I")
+                    # column order: r-, entropy, shear (ascending), r+
+                    assert R[d, i][0, 0] == 1.0 and R[d, i][0, 1] == 1.0 and R[d, i][0, K - 1] == 1.0
+            rng = np.random.default_rng(180 + dim)
+            X = rng.normal(size=(K, U.shape[1]))
+            for d in range(dim):
+                YL = o.char_apply(dim, d, 0, g, U, X)
+                YR = o.char_apply(dim, d, 1, g, U, X)
+                close(YL, np.einsum("nrc,cn->rn", L[d], X), 1e-14, "char_apply L")
+                close(YR, np.einsum("nrc,cn->rn", R[d], X), 1e-14, "char_apply R")
+                close(o.char_apply(dim, d, 1, g, U, YL), X, 1e-12, "R L = I")
+
+
 PINS = [
     pin_worked_state,
     pin_v_mag2,
@@ -491,4 +522,5 @@ PINS = [
     pin_riemann_characteristic,
     pin_characteristic_transform,
     pin_adjoint_fd,
+    pin_characteristic_decomposition,
 ]

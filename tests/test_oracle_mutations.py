@@ -41,6 +41,10 @@ MUTATIONS = [
     ("cons2char entropy", "W[1 * ldW + i] = s.p / pow(s.rho, gamma);", "W[1 * ldW + i] = s.p;"),
     ("v_mag2 divides by rho once", "y[i] = mm / (rho * rho);", "y[i] = mm / rho;"),
     ("v_mag2 drops a component", "for (k = 0; k < dim; ++k) {\n            double m", "for (k = 1; k < dim; ++k) {\n            double m"),
+    ("eigenvector acoustic sign", "Rm[K - 1][0] = H - cs * s->v[d];", "Rm[K - 1][0] = H + cs * s->v[d];"),
+    ("eigenvector entropy energy", "Rm[K - 1][1] = 0.5 * s->q;", "Rm[K - 1][1] = s->q;"),
+    ("eigenvector shear energy", "Rm[K - 1][col] = s->v[j];", "Rm[K - 1][col] = s->v[d];"),
+    ("char_apply uses R for L", "        if (mode == 0) {\n            if (invert", "        if (mode == 1) {\n            if (invert"),
     ("adjoint not transposed", "acc[c] = acc[c] + blk[r][c] * Fb[field * ldFb + i];",
      "acc[c] = acc[c] + blk[c][r] * Fb[field * ldFb + i];"),
     ("adjoint cotangent layout", "int64_t field = (dir >= 0) ? r : (r * dim + d);",
