@@ -83,7 +83,9 @@ typedef enum {
     FDBB_OP_FUSED = 8,
     FDBB_OP_ADJOINT = 9,
     FDBB_OP_V_MAG2 = 10,
-    FDBB_NUM_OPS = 11
+    FDBB_OP_EIGENVECTORS = 11,
+    FDBB_OP_CHAR_APPLY = 12,
+    FDBB_NUM_OPS = 13
 } fdbb_op;
 
 /* Conservative -> primitive (Sec. 2.2, "Variables", conversion figure):
@@ -157,6 +159,25 @@ int fdbb_euler_fused(int dim, double gamma, int dtype, const void *U, int64_t ld
 int fdbb_flux_adjoint(int dim, int dir, double gamma, int dtype, const void *U, int64_t ldU,
                       const void *Fbar, int64_t ldFbar, void *Ubar, int64_t ldUbar,
                       int64_t n, void *stream);
+
+/* Linearised characteristic decomposition A_d = R_d diag(v_d - c, v_d (D
+ * times), v_d + c) L_d of every direction (Fig. 1, "characteristic
+ * variables", in the linearised form that characteristic boundary
+ * conditions and limiters use).  The columns of R_d are the right
+ * eigenvectors, in the order of the characteristic variables of
+ * fdbb_cons2char: r- = (1, v - c e_d, H - c v_d), r0 = (1, v, |v|^2/2),
+ * r_j = (0, e_j, v_j) for j != d ascending, r+ = (1, v + c e_d, H + c v_d),
+ * with H = (E + p)/rho; L_d = R_d^{-1} in closed form.  Both are stored like
+ * the Jacobian blocks (point-major, row-major K x K, per-direction stride
+ * ldL / ldR points); either may be NULL (not both). */
+int fdbb_eigenvectors(int dim, double gamma, int dtype, const void *U, int64_t ldU, void *L, int64_t ldL,
+                      void *R, int64_t ldR, int64_t n, void *stream);
+
+/* Y = L_dir(U) X (mode 0: increments of the state to characteristic
+ * increments) or Y = R_dir(U) X (mode 1: back); X and Y have K fields.
+ * Y == X (same ld) works in place.  Not available as a batch task. */
+int fdbb_char_apply(int dim, int dir, int mode, double gamma, int dtype, const void *U, int64_t ldU,
+                    const void *X, int64_t ldX, void *Y, int64_t ldY, int64_t n, void *stream);
 
 /* ---------------------------------------------------------------- tuning
  * Launch configuration per (op, dim, dtype): `block` threads per workgroup

@@ -39,6 +39,7 @@ SOURCES = [
     "kernels_fused.hip",
     "kernels_adjoint.hip",
     "kernels_batch.hip",
+    "kernels_eigen.hip",
     "probes.hip",
 ]
 

@@ -143,6 +143,81 @@ __device__ __forceinline__ double jacobian_entry(const Gas &g, const double *v, 
     return t;
 }
 
+// Characteristic decomposition A_d = R diag(v_d - c, v_d.., v_d + c) L in
+// closed form.  Columns of R (rows of L) are ordered as the characteristic
+// variables: the v_d - c wave, the entropy wave, the shear waves j != d in
+// ascending j, the v_d + c wave.  With b = (gamma-1)/c^2:
+//   r-  = (1, v - c e_d, H - c v_d)      l-  = (b q/2 + v_d/c, -b v - e_d/c, b) / 2
+//   r0  = (1, v, q/2)                    l0  = (1 - b q/2, b v, -b)
+//   r_j = (0, e_j, v_j)                  l_j = (-v_j, e_j, 0)
+//   r+  = (1, v + c e_d, H + c v_d)      l+  = (b q/2 - v_d/c, -b v + e_d/c, b) / 2
+// (q = |v|^2).  Each l is orthogonal to every r of another wave and has
+// unit product with its own, which the reader can check row by column.
+struct Waves {
+    double c, inv_c, H, q, b;
+};
+
+template <int D>
+__device__ __forceinline__ int shear_axis(int slot, int d)
+{
+    return slot < d ? slot : slot + 1;
+}
+
+template <int D>
+__device__ __forceinline__ double right_entry(const double *v, const Waves &w, int d, int r, int col)
+{
+    constexpr int K = D + 2;
+    if (col == 0 || col == K - 1) {
+        const double sg = col == 0 ? -1.0 : 1.0;
+        if (r == 0) return 1.0;
+        if (r == K - 1) return w.H + sg * w.c * v[d];
+        return (r - 1 == d) ? v[r - 1] + sg * w.c : v[r - 1];
+    }
+    if (col == 1) {
+        if (r == 0) return 1.0;
+        if (r == K - 1) return 0.5 * w.q;
+        return v[r - 1];
+    }
+    const int j = shear_axis<D>(col - 2, d);
+    if (r == 0) return 0.0;
+    if (r == K - 1) return v[j];
+    return (r - 1 == j) ? 1.0 : 0.0;
+}
+
+template <int D>
+__device__ __forceinline__ double left_entry(const double *v, const Waves &w, int d, int row, int c)
+{
+    constexpr int K = D + 2;
+    if (row == 0 || row == K - 1) {
+        const double sg = row == 0 ? 1.0 : -1.0;
+        if (c == 0) return 0.5 * (0.5 * w.b * w.q + sg * v[d] * w.inv_c);
+        if (c == K - 1) return 0.5 * w.b;
+        const double t = -w.b * v[c - 1];
+        return 0.5 * ((c - 1 == d) ? t - sg * w.inv_c : t);
+    }
+    if (row == 1) {
+        if (c == 0) return 1.0 - 0.5 * w.b * w.q;
+        if (c == K - 1) return -w.b;
+        return w.b * v[c - 1];
+    }
+    const int j = shear_axis<D>(row - 2, d);
+    if (c == 0) return -v[j];
+    if (c == K - 1) return 0.0;
+    return (c - 1 == j) ? 1.0 : 0.0;
+}
+
+template <int D>
+__device__ __forceinline__ Waves make_waves(const Gas &g, const State<D> &s)
+{
+    Waves w;
+    w.c = sqrt(g.gamma * s.p * s.rinv);
+    w.inv_c = 1.0 / w.c;
+    w.H = (s.E + s.p) * s.rinv;
+    w.q = s.q;
+    w.b = g.g1 * w.inv_c * w.inv_c;
+    return w;
+}
+
 // Entropy s = p / rho^gamma.
 template <int D>
 __device__ __forceinline__ double entropy(const Gas &g, const State<D> &s)

@@ -16,6 +16,7 @@ constexpr int kWave = 64;
 enum : int32_t {
     kFlagInPlace = 1,  // K -> K transform with output == input: skip the rho store
     kFlagVector = 2,   // every base pointer and row stride allows 16-byte access
+    kFlagRight = 4,    // characteristic product with R (else with L)
 };
 
 // One operation on one field-set group (the device image of fdbb_task).
@@ -530,6 +531,40 @@ __device__ __forceinline__ void wave_copy_out(const T *lds, T *dst, int count, b
     }
 }
 
+// Stage this wave's 64 * P blocks of one K x K matrix per point in LDS
+// (entry(q, r, c) gives entry (r, c) of the thread's point q), then copy them
+// to `dst`, the global address of the wave's first block, as one contiguous
+// run.  Every thread of the workgroup must call this (it holds barriers).
+template <int D, typename T, int P, bool NT, class Entry>
+__device__ __forceinline__ void stage_blocks(const Lane<T, P, NT> &L, T *region, T *dst, int wave_pts,
+                                             Entry entry)
+{
+    constexpr int K = D + 2;
+    constexpr int KK = K * K;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        T *blk = region + L.local(q) * KK;
+#pragma unroll
+        for (int r = 0; r < K; ++r)
+#pragma unroll
+            for (int c = 0; c < K; ++c) blk[r * K + c] = (T)entry(q, r, c);
+        // one block at a time: keeps the scheduler from holding the entries
+        // of several blocks in registers at once
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+    if (wave_pts > 0) wave_copy_out<T, NT>(region, dst, wave_pts * KK, L.vec, L.lane);
+    __syncthreads();
+}
+
+// Points of the range in this wave's part of the tile.
+template <int P>
+__device__ __forceinline__ int wave_points(int64_t n, int64_t wave0)
+{
+    const int64_t left = n - wave0;
+    return left <= 0 ? 0 : (left >= kWave * P ? kWave * P : (int)left);
+}
+
 // The fused pass: flux tensor (out0, may be NULL), Jacobian blocks (out1,
 // may be NULL) and Riemann invariants (out2, may be NULL) of the same state.
 // Flux and invariants are stored chunk by chunk from the full state; the
@@ -577,28 +612,104 @@ __device__ __forceinline__ void tile_fused(const Args &a, int64_t tile0, T *lds)
 
     if (a.out1) {
         T *region = lds + (size_t)wave * kWave * P * KK;
-        const int64_t left = a.n - wave0;
-        const int wave_pts = left <= 0 ? 0 : (left >= kWave * P ? kWave * P : (int)left);
+        const int wave_pts = wave_points<P>(a.n, wave0);
         T *A = static_cast<T *>(a.out1);
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
+        for (int d = 0; d < D; ++d)
+            stage_blocks<D, T, P, NT>(L, region, A + (d * a.ld_out1 + wave0) * KK, wave_pts,
+                                      [&](int q, int r, int c) {
+                                          return jacobian_entry<D>(a.gas, jv[q], jphi[q], jH[q], d, r, c);
+                                      });
+    }
+}
+
+// Characteristic decomposition of every direction: left eigenvector blocks
+// L_d (out0, may be NULL) and right eigenvector blocks R_d (out1, may be
+// NULL), point-major K x K blocks like the Jacobian, staged through LDS.
+template <int D, typename T, int P, bool NT>
+__device__ __forceinline__ void tile_eigen(const Args &a, int64_t tile0, T *lds)
+{
+    constexpr int K = D + 2;
+    constexpr int KK = K * K;
+    using L_t = Lane<T, P, NT>;
+    constexpr int W = L_t::W, NC = L_t::NC;
+    const L_t L(a, tile0);
+    const int wave = threadIdx.x / kWave;
+    const int64_t wave0 = tile0 + (int64_t)wave * kWave * P;
+
+    double u[NC][K][W];
 #pragma unroll
-            for (int q = 0; q < P; ++q) {
-                T *blk = region + L.local(q) * KK;
+    for (int c = 0; c < NC; ++c) L.template load_fields<K>(a.in0, a.ld_in0, c, u[c]);
+    double v[P][D];
+    Waves w[P];
 #pragma unroll
-                for (int r = 0; r < K; ++r)
+    for (int c = 0; c < NC; ++c) {
 #pragma unroll
-                    for (int c = 0; c < K; ++c)
-                        blk[r * K + c] = (T)jacobian_entry<D>(a.gas, jv[q], jphi[q], jH[q], d, r, c);
-                // one block at a time: keeps the scheduler from holding the
-                // entries of several blocks in registers at once
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            __syncthreads();
-            if (wave_pts > 0)
-                wave_copy_out<T, NT>(region, A + (d * a.ld_out1 + wave0) * KK, wave_pts * KK, L.vec, L.lane);
-            __syncthreads();
+        for (int j = 0; j < W; ++j) {
+            double uj[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) uj[k] = u[c][k][j];
+            const State<D> s = make_state<D>(a.gas, uj);
+            const int q = c * W + j;
+#pragma unroll
+            for (int k = 0; k < D; ++k) v[q][k] = s.v[k];
+            w[q] = make_waves<D>(a.gas, s);
         }
+    }
+    T *region = lds + (size_t)wave * kWave * P * KK;
+    const int wave_pts = wave_points<P>(a.n, wave0);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        if (a.out0)
+            stage_blocks<D, T, P, NT>(L, region, static_cast<T *>(a.out0) + (d * a.ld_out0 + wave0) * KK,
+                                      wave_pts,
+                                      [&](int q, int r, int c) { return left_entry<D>(v[q], w[q], d, r, c); });
+        if (a.out1)
+            stage_blocks<D, T, P, NT>(L, region, static_cast<T *>(a.out1) + (d * a.ld_out1 + wave0) * KK,
+                                      wave_pts,
+                                      [&](int q, int r, int c) { return right_entry<D>(v[q], w[q], d, r, c); });
+    }
+}
+
+// Y = L_dir(U) X, or R_dir(U) X with kFlagRight: in0 = U, in1 = X, out0 = Y.
+template <int D, typename T, int P, bool NT>
+__device__ __forceinline__ void tile_char_apply(const Args &a, int64_t tile0)
+{
+    constexpr int K = D + 2;
+    using L_t = Lane<T, P, NT>;
+    constexpr int W = L_t::W, NC = L_t::NC;
+    const L_t L(a, tile0);
+    if (!L.any()) return;
+    const bool right = (a.flags & kFlagRight) != 0;
+    const int dir = a.dir;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double u[K][W], x[K][W], y[K][W];
+        L.template load_fields<K>(a.in0, a.ld_in0, c, u);
+        L.template load_fields<K>(a.in1, a.ld_in1, c, x);
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            double uj[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) uj[k] = u[k][j];
+            const State<D> s = make_state<D>(a.gas, uj);
+            const Waves wv = make_waves<D>(a.gas, s);
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+                double acc = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    if (d != dir) continue;
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        acc += (right ? right_entry<D>(s.v, wv, d, r, k) : left_entry<D>(s.v, wv, d, r, k)) *
+                               x[k][j];
+                }
+                y[r][j] = acc;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < K; ++r) L.store(a.out0, a.ld_out0, r, c, y[r]);
     }
 }
 

@@ -173,7 +173,8 @@ struct Call {
     Args a{};
     std::vector<Range> ranges;  // for alias checks
     bool inplace_ok = false;    // K -> K transform
-    size_t unit_out1 = 1;       // elements per point of out1 (K*K for Jacobian blocks)
+    size_t unit_out0 = 1;       // elements per point of out0 (K*K for blocks)
+    size_t unit_out1 = 1;       // elements per point of out1 (K*K for blocks)
 };
 
 // Register one field set: checks NULL, ld and alignment.
@@ -217,7 +218,7 @@ bool vector_ok(const Call &c)
     for (int k = 0; k < 5; ++k) {
         if (!bases[k]) continue;
         if ((uintptr_t)bases[k] % 16 != 0) return false;
-        const size_t unit = (k == 3) ? c.unit_out1 : 1;
+        const size_t unit = (k == 3) ? c.unit_out1 : (k == 2 ? c.unit_out0 : 1);
         if (((size_t)lds[k] * unit * es) % 16 != 0) return false;
     }
     return true;
@@ -237,6 +238,8 @@ int family_of(int op)
     case FDBB_OP_FUSED: return kFamFused;
     case FDBB_OP_ADJOINT: return kFamAdjoint;
     case FDBB_OP_V_MAG2: return kFamVmag2;
+    case FDBB_OP_EIGENVECTORS: return kFamEigen;
+    case FDBB_OP_CHAR_APPLY: return kFamCharApply;
     default: return -1;
     }
 }
@@ -255,13 +258,17 @@ const void *kernel_for(int op, int dim, int dtype, int ppt, bool nt)
     case kFamChar2Cons: return kernel_char(fam, dim, dtype, ppt, nt);
     case kFamFused: return kernel_fused(dim, dtype, ppt, nt);
     case kFamAdjoint: return kernel_adjoint(dim, dtype, ppt, nt);
+    case kFamEigen:
+    case kFamCharApply: return kernel_eigen(fam, dim, dtype, ppt, nt);
     default: return nullptr;
     }
 }
 
+bool stages_blocks(int op) { return family_of(op) == kFamFused || family_of(op) == kFamEigen; }
+
 size_t lds_bytes(int op, int dim, int dtype, int block, int ppt)
 {
-    if (family_of(op) != kFamFused) return 0;
+    if (!stages_blocks(op)) return 0;
     // Jacobian blocks only need staging when they are written.
     const size_t K = (size_t)dim + 2;
     return (size_t)block * ppt * K * K * elem_size(dtype);
@@ -292,7 +299,8 @@ int launch(Call &c, void *stream)
     DeviceInfo dev;
     rc = device_info(&dev);
     if (rc) return rc;
-    const bool needs_lds = (c.op == FDBB_OP_FLUX_JACOBIAN) || (c.op == FDBB_OP_FUSED && c.a.out1);
+    const bool needs_lds = (c.op == FDBB_OP_FLUX_JACOBIAN) || (c.op == FDBB_OP_FUSED && c.a.out1) ||
+                           (c.op == FDBB_OP_EIGENVECTORS);
     const size_t lds = needs_lds ? lds_bytes(c.op, c.dim, c.dtype, cfg.block, cfg.ppt) : 0;
     rc = set_lds_attr(fn, lds, dev);
     if (rc) return rc;
@@ -323,8 +331,9 @@ int begin(Call &c, int op, int dim, double gamma, int dtype, int64_t n)
 }
 
 // Fills c for any op from the task-style argument list; shared by the
-// single-call entry points and the batch plans.
-int build_call(Call &c, const fdbb_task &t)
+// single-call entry points and the batch plans.  `mode` selects R (1) or L
+// (0) for the characteristic products.
+int build_call(Call &c, const fdbb_task &t, int mode = 0)
 {
     int rc = begin(c, t.op, t.dim, t.gamma, t.dtype, t.n);
     if (rc) return rc;
@@ -360,6 +369,27 @@ int build_call(Call &c, const fdbb_task &t)
         a.in0 = t.in0, a.ld_in0 = t.ld_in0, a.out0 = t.out0, a.ld_out0 = t.ld_out0;
         if ((rc = add_fields(c, t.in0, t.ld_in0, K, 1, true, true, "U"))) return rc;
         if ((rc = add_fields(c, t.out0, t.ld_out0, (int64_t)K * D, 1, false, true, "F"))) return rc;
+        break;
+    case FDBB_OP_EIGENVECTORS:
+        if (!t.out0 && !t.out1 && t.n > 0) return fail(FDBB_EINVAL, "L and R must not both be NULL");
+        c.unit_out0 = c.unit_out1 = (size_t)K * K;
+        a.in0 = t.in0, a.ld_in0 = t.ld_in0;
+        a.out0 = t.out0, a.ld_out0 = t.ld_out0, a.out1 = t.out1, a.ld_out1 = t.ld_out1;
+        if ((rc = add_fields(c, t.in0, t.ld_in0, K, 1, true, true, "U"))) return rc;
+        if ((rc = add_fields(c, t.out0, t.ld_out0, D, (int64_t)K * K, false, false, "L"))) return rc;
+        if ((rc = add_fields(c, t.out1, t.ld_out1, D, (int64_t)K * K, false, false, "R"))) return rc;
+        break;
+    case FDBB_OP_CHAR_APPLY:
+        if (t.dir < 0 || t.dir >= D) return fail(FDBB_EINVAL, "dir out of range");
+        if (mode != 0 && mode != 1) return fail(FDBB_EINVAL, "mode must be 0 (L) or 1 (R)");
+        a.dir = t.dir;
+        if (mode == 1) a.flags |= kFlagRight;
+        c.inplace_ok = true;
+        a.in0 = t.in0, a.ld_in0 = t.ld_in0, a.in1 = t.in1, a.ld_in1 = t.ld_in1;
+        a.out0 = t.out0, a.ld_out0 = t.ld_out0;
+        if ((rc = add_fields(c, t.in0, t.ld_in0, K, 1, true, true, "U"))) return rc;
+        if ((rc = add_fields(c, t.in1, t.ld_in1, K, 1, true, true, "X"))) return rc;
+        if ((rc = add_fields(c, t.out0, t.ld_out0, K, 1, false, true, "Y"))) return rc;
         break;
     case FDBB_OP_V_MAG2:
         a.in0 = t.in0, a.ld_in0 = t.ld_in0, a.out0 = t.out0;
@@ -418,10 +448,10 @@ fdbb_task make_task(int op, int dim, int dir, double gamma, int dtype, int64_t n
     return t;
 }
 
-int run(const fdbb_task &t, void *stream)
+int run(const fdbb_task &t, void *stream, int mode = 0)
 {
     Call c;
-    int rc = build_call(c, t);
+    int rc = build_call(c, t, mode);
     if (rc) return rc;
     return launch(c, stream);
 }
@@ -523,13 +553,29 @@ int fdbb_flux_adjoint(int dim, int dir, double gamma, int dtype, const void *U, 
     return run(t, stream);
 }
 
+int fdbb_eigenvectors(int dim, double gamma, int dtype, const void *U, int64_t ldU, void *L, int64_t ldL,
+                      void *R, int64_t ldR, int64_t n, void *stream)
+{
+    fdbb_task t = make_task(FDBB_OP_EIGENVECTORS, dim, 0, gamma, dtype, n);
+    t.in0 = U, t.ld_in0 = ldU, t.out0 = L, t.ld_out0 = ldL, t.out1 = R, t.ld_out1 = ldR;
+    return run(t, stream);
+}
+
+int fdbb_char_apply(int dim, int dir, int mode, double gamma, int dtype, const void *U, int64_t ldU,
+                    const void *X, int64_t ldX, void *Y, int64_t ldY, int64_t n, void *stream)
+{
+    fdbb_task t = make_task(FDBB_OP_CHAR_APPLY, dim, dir, gamma, dtype, n);
+    t.in0 = U, t.ld_in0 = ldU, t.in1 = X, t.ld_in1 = ldX, t.out0 = Y, t.ld_out0 = ldY;
+    return run(t, stream, mode);
+}
+
 int fdbb_set_launch_config(int op, int dim, int dtype, int block, int ppt, int grid_cap, int nontemporal)
 {
     if (op < 0 || op >= FDBB_NUM_OPS || dim < 1 || dim > 3 || (dtype != FDBB_F64 && dtype != FDBB_F32))
         return fail(FDBB_EINVAL, "unknown op, dim or dtype");
     if (!config_ok(block, ppt, grid_cap, nontemporal)) return fail(FDBB_EINVAL, "invalid launch configuration");
-    if (family_of(op) == kFamFused && block > kMaxBlockStaged)
-        return fail(FDBB_EINVAL, "Jacobian kernels take at most 256 threads per workgroup");
+    if (stages_blocks(op) && block > kMaxBlockStaged)
+        return fail(FDBB_EINVAL, "kernels that stage K x K blocks take at most 256 threads per workgroup");
     std::call_once(g_cfg_once, init_configs);
     Config c{block, ppt, grid_cap, nontemporal};
     g_cfg[op][dim - 1][dtype].store(pack(c));
@@ -630,6 +676,8 @@ int stage_tasks(fdbb_batch_plan *p, const fdbb_task *tasks, int ntasks)
     std::vector<Range> all;
     size_t need_lds = 0;
     for (int b = 0; b < ntasks; ++b) {
+        if (tasks[b].op == FDBB_OP_EIGENVECTORS || tasks[b].op == FDBB_OP_CHAR_APPLY)
+            return fail(FDBB_EINVAL, "task " + std::to_string(b) + ": op not available in batches");
         int rc = build_call(calls[b], tasks[b]);
         if (rc) return fail(rc, "task " + std::to_string(b) + ": " + g_last_error);
         rc = check_alias(calls[b]);
@@ -732,6 +780,8 @@ int fdbb_batch_plan_create(const fdbb_task *tasks, int ntasks, int capacity, int
     if (ntasks > 0 && !tasks) return fail(FDBB_EINVAL, "tasks must not be NULL");
     // Argument checks of every task come before any HIP call.
     for (int b = 0; b < ntasks; ++b) {
+        if (tasks[b].op == FDBB_OP_EIGENVECTORS || tasks[b].op == FDBB_OP_CHAR_APPLY)
+            return fail(FDBB_EINVAL, "task " + std::to_string(b) + ": op not available in batches");
         Call c;
         int rc = build_call(c, tasks[b]);
         if (!rc) rc = check_alias(c);

@@ -39,6 +39,8 @@ enum Family : int {
     kFamFused,  // fused pass and flux Jacobian (F and R NULL)
     kFamAdjoint,
     kFamVmag2,
+    kFamEigen,      // eigenvector blocks (staged like the Jacobian)
+    kFamCharApply,  // products with L or R of one direction
     kNumFamilies
 };
 
@@ -48,6 +50,7 @@ const void *kernel_pointwise(int family, int dim, int dtype, int ppt, bool nt);
 const void *kernel_char(int family, int dim, int dtype, int ppt, bool nt);
 const void *kernel_fused(int dim, int dtype, int ppt, bool nt);
 const void *kernel_adjoint(int dim, int dtype, int ppt, bool nt);
+const void *kernel_eigen(int family, int dim, int dtype, int ppt, bool nt);
 
 // Persistent batch kernel: void k(const TaskDev*, const int64_t* prefix,
 // const int64_t* header).  header = {ntasks, ntiles}; prefix has ntasks + 1

@@ -27,7 +27,7 @@ OK, EINVAL, EALIGN, EALIAS, EHIP, ENOMEM = range(6)
 OPS = {
     "cons2prim": 0, "prim2cons": 1, "eos": 2, "flux": 3, "flux_jacobian": 4,
     "riemann_invariants": 5, "cons2char": 6, "char2cons": 7, "fused": 8, "adjoint": 9,
-    "v_mag2": 10,
+    "v_mag2": 10, "eigenvectors": 11, "char_apply": 12,
 }
 ROW_ALIGN = 64  # elements; keeps every row 16-byte aligned for both dtypes
 
@@ -74,6 +74,8 @@ def library():
             getattr(lib, name).argtypes = [_i, _i, _d, _i, _p, _i64, _p, _i64, _i64, _p]
         lib.fdbb_euler_fused.argtypes = [_i, _d, _i, _p, _i64, _p, _i64, _p, _i64, _p, _i64, _i64, _p]
         lib.fdbb_flux_adjoint.argtypes = [_i, _i, _d, _i, _p, _i64, _p, _i64, _p, _i64, _i64, _p]
+        lib.fdbb_eigenvectors.argtypes = [_i, _d, _i, _p, _i64, _p, _i64, _p, _i64, _i64, _p]
+        lib.fdbb_char_apply.argtypes = [_i, _i, _i, _d, _i, _p, _i64, _p, _i64, _p, _i64, _i64, _p]
         lib.fdbb_set_launch_config.argtypes = [_i, _i, _i, _i, _i, _i, _i]
         lib.fdbb_get_launch_config.argtypes = [_i, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i),
                                                ctypes.POINTER(_i), ctypes.POINTER(_i)]
@@ -268,6 +270,24 @@ def fdbb_flux_adjoint(dim, direction, gamma, U, Fbar, Ubar, n=None, stream=None)
                                       ub, ldub, n, _stream(stream)))
 
 
+def fdbb_eigenvectors(dim, gamma, U, L=None, R=None, n=None, stream=None):
+    u, ldu = _fields(U, dim + 2, "U")
+    lp, ldl = _blocks(L, dim, "L") if L is not None else (None, 0)
+    rp, ldr = _blocks(R, dim, "R") if R is not None else (None, 0)
+    n = U.shape[1] if n is None else n
+    check(library().fdbb_eigenvectors(dim, gamma, dtype_code(U.dtype), u, ldu, lp, ldl, rp, ldr, n,
+                                      _stream(stream)))
+
+
+def fdbb_char_apply(dim, direction, mode, gamma, U, X, Y, n=None, stream=None):
+    u, ldu = _fields(U, dim + 2, "U")
+    x, ldx = _fields(X, dim + 2, "X")
+    y, ldy = _fields(Y, dim + 2, "Y")
+    n = U.shape[1] if n is None else n
+    check(library().fdbb_char_apply(dim, direction, mode, gamma, dtype_code(U.dtype), u, ldu, x, ldx, y, ldy,
+                                    n, _stream(stream)))
+
+
 def fdbb_set_launch_config(op, dim, dtype, block, ppt, grid_cap=0, nontemporal=1):
     op = OPS[op] if isinstance(op, str) else op
     check(library().fdbb_set_launch_config(op, dim, dtype, block, ppt, grid_cap, nontemporal))
@@ -394,3 +414,20 @@ def probe_read(src: torch.Tensor, sink: torch.Tensor, grid: int = 0, stream=None
     nbytes = src.numel() * src.element_size()
     check(library().fdbb_probe_read(src.data_ptr(), nbytes // 16 * 16, sink.data_ptr(), grid,
                                     _stream(stream)))
+
+
+def eigenvectors(U, gamma=1.4, left=True, right=True, stream=None):
+    """(L, R) eigenvector blocks of every direction, (D, n, K, K) each."""
+    dim = _dim_of(U)
+    L = empty_blocks(dim, U.shape[1], U.dtype, U.device) if left else None
+    R = empty_blocks(dim, U.shape[1], U.dtype, U.device) if right else None
+    fdbb_eigenvectors(dim, gamma, U, L, R, stream=stream)
+    return L, R
+
+
+def char_apply(U, X, direction, mode=0, gamma=1.4, stream=None):
+    """L_dir(U) X (mode 0) or R_dir(U) X (mode 1)."""
+    dim = _dim_of(U)
+    Y = empty_fields(dim + 2, U.shape[1], U.dtype, U.device)
+    fdbb_char_apply(dim, direction, mode, gamma, U, X, Y, stream=stream)
+    return Y

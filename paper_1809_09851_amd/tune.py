@@ -91,6 +91,13 @@ def workload(op: str, dim: int, dtype, n: int):
         W = F.empty_fields(K, n, dtype)
         F.fdbb_cons2char(dim, 0, GAMMA, U, W)
         return lambda: F.fdbb_char2cons(dim, 0, GAMMA, W, U)
+    if op == "eigenvectors":
+        L, R = F.empty_blocks(dim, n, dtype), F.empty_blocks(dim, n, dtype)
+        return lambda: F.fdbb_eigenvectors(dim, GAMMA, U, L, R)
+    if op == "char_apply":
+        X = F.empty_fields(K, n, dtype).normal_()
+        Y = F.empty_fields(K, n, dtype)
+        return lambda: F.fdbb_char_apply(dim, 0, 0, GAMMA, U, X, Y)
     if op == "adjoint":
         Fb = F.empty_fields(K * dim, n, dtype).normal_()
         Ub = F.empty_fields(K, n, dtype)

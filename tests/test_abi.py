@@ -108,6 +108,15 @@ def test_direction_checks():
     assert lib.fdbb_flux_adjoint(3, -2, 1.4, 0, A0, 128, B0, 128, A0 + 10**7, 128, 100, None) == F.EINVAL
 
 
+def test_eigen_and_char_apply_checks():
+    lib = F.library()
+    assert lib.fdbb_eigenvectors(3, 1.4, 0, A0, 128, None, 0, None, 0, 100, None) == F.EINVAL
+    assert lib.fdbb_eigenvectors(2, 1.4, 0, A0, 128, A0, 128, None, 0, 100, None) == F.EALIAS
+    assert lib.fdbb_char_apply(2, 2, 0, 1.4, 0, A0, 128, B0, 128, B0 + 10**6, 128, 100, None) == F.EINVAL
+    assert lib.fdbb_char_apply(2, 0, 2, 1.4, 0, A0, 128, B0, 128, B0 + 10**6, 128, 100, None) == F.EINVAL
+    assert lib.fdbb_char_apply(2, 0, 0, 1.4, 0, A0, 128, B0, 128, B0 + 8, 128, 100, None) == F.EALIAS
+
+
 def test_launch_config_table():
     lib = F.library()
     assert lib.fdbb_set_launch_config(3, 3, 0, 100, 1, 0, 1) == F.EINVAL   # not a multiple of 64

@@ -197,6 +197,38 @@ def test_adjoint(dim, dt, n):
         assert err <= TOL[dt], (direction, err)
 
 
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("dim", DIMS)
+@pytest.mark.parametrize("n", SIZES)
+def test_eigenvectors(dim, dt, n):
+    Uo, Ug = states(dim, n, _seed(dim, n, dt, 14), dt)
+    L, R = F.eigenvectors(Ug, GAMMA)
+    Lo, Ro = oracle.eigenvectors(dim, GAMMA, Uo)
+    assert blocks_error(host(L), Lo) <= TOL[dt]
+    assert blocks_error(host(R), Ro) <= TOL[dt]
+    Lg, _ = F.eigenvectors(Ug, GAMMA, right=False)
+    assert blocks_error(host(Lg), Lo) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("dim", DIMS)
+@pytest.mark.parametrize("n", (1, 65, 5003))
+def test_char_apply(dim, dt, n):
+    from paper_1809_09851_amd import inputs
+    Uo, Ug = states(dim, n, _seed(dim, n, dt, 15), dt)
+    K = dim + 2
+    X = inputs.cotangent(dim, n, _seed(dim, n, dt, 16), fields=K)
+    X = X.astype(np.float32 if dt == "f32" else np.float64).astype(np.float64)
+    Xg = F.to_fields(torch.from_numpy(X).to(DTYPES[dt]).cuda())
+    Lo, Ro = oracle.eigenvectors(dim, GAMMA, Uo)
+    for d in range(dim):
+        for mode, M in ((0, Lo[d]), (1, Ro[d])):
+            Y = F.char_apply(Ug, Xg, d, mode, GAMMA)
+            ref = oracle.char_apply(dim, d, mode, GAMMA, Uo, X)
+            den = np.einsum("nrc,cn->rn", np.abs(M), np.abs(X)).max(axis=0)
+            assert group_error(host(Y), ref, [list(range(K))], denom=den) <= TOL[dt], (d, mode)
+
+
 # ------------------------------------------------------------ edge cases
 
 def test_zero_points_leave_outputs_untouched():
