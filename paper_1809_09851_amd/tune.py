@@ -134,11 +134,11 @@ def search(op: str, dim: int, dt: str, n: int, reps: int = 7, space=None, verbos
         # kernels that spill registers move extra bytes through HBM; skip them
         if F.fdbb_kernel_info(op, dim, code, cfg[1], cfg[3])[1] > 0:
             continue
-        F.fdbb_set_launch_config(op, dim, code, *cfg)
         try:
+            F.fdbb_set_launch_config(op, dim, code, *cfg)
             ms = time_launch(fn, reps)
         except F.FdbbError:
-            continue  # e.g. more LDS than a workgroup may hold
+            continue  # a configuration this kernel cannot take (block size, LDS)
         results.append((ms, cfg))
         if verbose:
             print(f"  {op} {dim}d {dt} n={n} cfg={cfg} {ms:.4f} ms", file=sys.stderr, flush=True)

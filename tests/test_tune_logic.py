@@ -1,0 +1,54 @@
+"""The autotuner's search on the CPU: timing and kernel queries are faked,
+the launch-configuration table is the real library's (host-only calls)."""
+import json
+
+from paper_1809_09851_amd import fdbb as F
+from paper_1809_09851_amd import tune
+
+
+def _fake(monkeypatch, spill_ppt4=True):
+    monkeypatch.setattr(tune, "workload", lambda op, dim, dtype, n: (lambda: None))
+    calls = []
+
+    def fake_time(fn, reps=7, warmup=2):
+        cfg = F.fdbb_get_launch_config(calls[-1][0], calls[-1][1], calls[-1][2])
+        block, ppt, cap, nt = cfg
+        return 1.0 + abs(block - 256) / 1000.0 + (0.5 if cap else 0.0) + (0.01 if nt else 0.0) + ppt / 100.0
+
+    def fake_info(op, dim, dtype, ppt, nt=1):
+        calls.append((op, dim, dtype))
+        return (128, 64 if (spill_ppt4 and ppt == 4) else 0)
+
+    monkeypatch.setattr(tune, "time_launch", fake_time)
+    monkeypatch.setattr(F, "fdbb_kernel_info", fake_info)
+
+
+def test_search_skips_invalid_and_spilling_configs(monkeypatch):
+    _fake(monkeypatch)
+    old = F.fdbb_get_launch_config("flux_jacobian", 3, F.F64)
+    try:
+        res = tune.search("flux_jacobian", 3, "f64", 1 << 20)
+        cfgs = [c for _, c in res]
+        assert all(c[0] <= 256 for c in cfgs)          # staged kernels: at most 256 threads
+        assert all(c[1] != 4 for c in cfgs)            # spilling kernels skipped
+        assert res[0][1] == (256, 1, 0, 0)             # fastest under the fake clock
+        assert F.fdbb_get_launch_config("flux_jacobian", 3, F.F64) == (256, 1, 0, 0)
+    finally:
+        F.fdbb_set_launch_config("flux_jacobian", 3, F.F64, *old)
+
+
+def test_table_round_trip(tmp_path, monkeypatch):
+    p = tmp_path / "t.json"
+    key = "gfx950/hiptest"
+    p.write_text(json.dumps({key: {
+        "flux/3/f64": {"block": 128, "ppt": 2, "grid_cap": 0, "nt": 0},
+        "fused/3/f64": {"block": 1024, "ppt": 1, "grid_cap": 0, "nt": 0},   # invalid: ignored
+    }}))
+    old = F.fdbb_get_launch_config("flux", 3, F.F64)
+    oldf = F.fdbb_get_launch_config("fused", 3, F.F64)
+    try:
+        assert tune.apply_table(str(p), key=key) == 1
+        assert F.fdbb_get_launch_config("flux", 3, F.F64) == (128, 2, 0, 0)
+        assert F.fdbb_get_launch_config("fused", 3, F.F64) == oldf
+    finally:
+        F.fdbb_set_launch_config("flux", 3, F.F64, *old)
