@@ -84,8 +84,9 @@ class Server:
     """
 
     def __init__(self, executor, budget_bytes: int, slots: int | None, max_batch: int = 64,
-                 clock=time.perf_counter):
+                 clock=time.perf_counter, on_complete=None):
         self.ex = executor
+        self.on_complete = on_complete  # called with each request as it completes
         self.budget = int(budget_bytes)
         self.used = 0
         self.peak_used = 0
@@ -121,6 +122,8 @@ class Server:
                 r.t_done = now
                 self.used -= r.out_bytes
                 self.completed.append(r)
+                if self.on_complete is not None:
+                    self.on_complete(r)
             release = getattr(self.ex, "release", None)
             if release:
                 release(s)
@@ -367,12 +370,17 @@ def serve_benchmark(rate: float, count: int, warmup: int = 200, slots: int = 4, 
     pools = pools or StatePools()
     specs = inputs.request_stream(rate, warmup + count, seed=seed, pool=pools.pool)
     reqs = [pools.request(s) for s in specs]
+    def release(r):
+        # a served result is handed on; the benchmark drops it at once, so
+        # HBM held by outputs is what the budget accounts for
+        r.out = None
+
     if baseline:
         ex = SingleLaunchExecutor()
-        srv = Server(ex, budget, slots=None, max_batch=1)
+        srv = Server(ex, budget, slots=None, max_batch=1, on_complete=release)
     else:
         ex = GpuBatchExecutor(slots)
-        srv = Server(ex, budget, slots=slots, max_batch=max_batch)
+        srv = Server(ex, budget, slots=slots, max_batch=max_batch, on_complete=release)
     done = srv.run_arrivals(reqs)
     torch.cuda.synchronize()
     measured = [r for r in done if r.rid >= warmup]

@@ -15,6 +15,7 @@ from __future__ import annotations
 import argparse
 import itertools
 import json
+import math
 import os
 import statistics
 import sys
@@ -105,6 +106,24 @@ def workload(op: str, dim: int, dtype, n: int):
     raise ValueError(op)
 
 
+def bytes_per_point(op: str, dim: int, elem: int) -> int:
+    """Algorithmic HBM bytes per point of one launch of `op`."""
+    K = dim + 2
+    per = {"cons2prim": 2 * K, "prim2cons": 2 * K, "cons2char": 2 * K, "char2cons": 2 * K,
+           "eos": K + 2, "v_mag2": dim + 2, "flux": K + K * dim, "flux_jacobian": K + dim * K * K,
+           "riemann_invariants": K + 2 * dim + 1, "fused": K + K * dim + dim * K * K + 2 * dim + 1,
+           "adjoint": K * K, "eigenvectors": K + 2 * dim * K * K, "char_apply": 3 * K}[op]
+    return per * elem
+
+
+def auto_size(op: str, dim: int, elem: int, target_bytes: float = 2e9) -> int:
+    """A size whose working set (about 2 GB) is far larger than the 256 MB
+    last-level cache, so that the search sees HBM behaviour."""
+    n = target_bytes / bytes_per_point(op, dim, elem)
+    e = min(27, max(22, int(round(math.log2(n)))))
+    return 1 << e
+
+
 def time_launch(fn, reps: int = 7, warmup: int = 2) -> float:
     """Median milliseconds of one launch, HIP events on the current stream."""
     for _ in range(warmup):
@@ -184,7 +203,8 @@ def main(argv=None):
     ap.add_argument("--ops", default="fused")
     ap.add_argument("--dims", default="3")
     ap.add_argument("--dtypes", default="f64,f32")
-    ap.add_argument("--n", type=int, default=1 << 24)
+    ap.add_argument("--n", default="auto",
+                    help="points per launch, or 'auto' for a working set of about 2 GB per op")
     ap.add_argument("--reps", type=int, default=7)
     ap.add_argument("--write", default=None, help="merge results into this JSON table")
     ap.add_argument("--verbose", action="store_true")
@@ -196,12 +216,13 @@ def main(argv=None):
     for op in args.ops.split(","):
         for dim in (int(d) for d in args.dims.split(",")):
             for dt in args.dtypes.split(","):
-                res = search(op, dim, dt, args.n, args.reps, verbose=args.verbose)
+                n = (auto_size(op, dim, 8 if dt == "f64" else 4) if args.n == "auto" else int(args.n))
+                res = search(op, dim, dt, n, args.reps, verbose=args.verbose)
                 best_ms, (block, ppt, cap, nt) = res[0]
                 base = [ms for ms, cfg in res if cfg == (256, 1 if op in ("fused", "flux_jacobian") else
                                                          (2 if dt == "f64" else 4), 0, 1)]
                 entries[f"{op}/{dim}/{dt}"] = {"block": block, "ppt": ppt, "grid_cap": cap, "nt": nt,
-                                               "ms": round(best_ms, 5), "n": args.n,
+                                               "ms": round(best_ms, 5), "n": n,
                                                "default_ms": round(base[0], 5) if base else None,
                                                "top5": [[round(ms, 5), list(c)] for ms, c in res[:5]]}
                 print(json.dumps({f"{op}/{dim}/{dt}": entries[f"{op}/{dim}/{dt}"]}), flush=True)
