@@ -254,7 +254,7 @@ def bench_autograd(steps: int, warmup: int):
     return {"n": n, "ms_per_fwd_bwd": round(wall, 4), "gpoints_s": round(n / (wall * 1e-3) / 1e9, 3)}
 
 
-def bench_serving(rates, count: int, warmup: int):
+def bench_serving(rates, count: int, warmup: int, slots: int = 8, batch_mb: float = 64.0):
     """Poisson request streams: continuous batching against one launch per
     request on a single stream (same requests, same pools)."""
     from paper_1809_09851_amd import serve as S
@@ -262,7 +262,8 @@ def bench_serving(rates, count: int, warmup: int):
     out = []
     for rate in rates:
         for baseline in (False, True):
-            r = S.serve_benchmark(rate, count, warmup=warmup, pools=pools, baseline=baseline)
+            r = S.serve_benchmark(rate, count, warmup=warmup, pools=pools, baseline=baseline, slots=slots,
+                                  max_batch_bytes=batch_mb * 1e6)
             print(f"# serving rate={rate:g} {'baseline' if baseline else 'batched'}: "
                   f"p50 {r['p50_ms']} ms p99 {r['p99_ms']} ms, {r['req_s']} req/s",
                   file=sys.stderr, flush=True)
@@ -397,6 +398,9 @@ def main(argv=None):
                     help="comma-separated Poisson rates (req/s) for the serving measurement; '' skips it")
     ap.add_argument("--serve-count", type=int, default=1000)
     ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-batch-mb", type=float, default=64.0,
+                    help="HBM megabytes one batched launch may move")
     ap.add_argument("--paper-sweeps", action="store_true",
                     help="also run the paper's micro-benchmark and mini-application sweeps (N = 2^10..2^28)")
     ap.add_argument("--probe-copy", action="store_true",
@@ -461,7 +465,8 @@ def main(argv=None):
         line["paper_sweeps"] = bench_paper_sweeps()
     rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
     if rates:
-        line["serving"] = bench_serving(rates, args.serve_count, args.serve_warmup)
+        line["serving"] = bench_serving(rates, args.serve_count, args.serve_warmup, args.serve_slots,
+                                        args.serve_batch_mb)
     if args.probe_copy:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
         b = torch.empty_like(a)

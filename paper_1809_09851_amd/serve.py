@@ -78,14 +78,18 @@ class Request:
 class Server:
     """Continuous-batching scheduler.
 
-    budget_bytes  HBM the outputs of in-flight requests may hold together
-    slots         launch slots (batches in flight at once); None = unlimited
-    max_batch     requests per launch
+    budget_bytes     HBM the outputs of in-flight requests may hold together
+    slots            launch slots (batches in flight at once); None = unlimited
+    max_batch        requests per launch
+    max_batch_bytes  HBM bytes one launch may move; a request that would
+                     push a non-empty batch past it starts the next batch,
+                     so small requests are not held behind a large one
     """
 
     def __init__(self, executor, budget_bytes: int, slots: int | None, max_batch: int = 64,
-                 clock=time.perf_counter, on_complete=None):
+                 clock=time.perf_counter, on_complete=None, max_batch_bytes: float = float("inf")):
         self.ex = executor
+        self.max_batch_bytes = max_batch_bytes
         self.on_complete = on_complete  # called with each request as it completes
         self.budget = int(budget_bytes)
         self.used = 0
@@ -145,11 +149,16 @@ class Server:
         next request's outputs fit in what is left of the budget."""
         started = 0
         while self.queue and self._slot_available():
-            batch = []
+            batch, moved = [], 0
             while (self.queue and len(batch) < self.max_batch
                    and self.used + self.queue[0].out_bytes <= self.budget):
-                r = self.queue.popleft()
+                r = self.queue[0]
+                m = moved_bytes(r.op, r.dim, r.n, r.elem)
+                if batch and moved + m > self.max_batch_bytes:
+                    break
+                self.queue.popleft()
                 self.used += r.out_bytes
+                moved += m
                 batch.append(r)
             if not batch:
                 break
@@ -359,9 +368,9 @@ def summarize(done, t_span: float | None = None):
             "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4)}
 
 
-def serve_benchmark(rate: float, count: int, warmup: int = 200, slots: int = 4, max_batch: int = 64,
+def serve_benchmark(rate: float, count: int, warmup: int = 200, slots: int = 8, max_batch: int = 64,
                     budget: int = 200 * 10 ** 9, pools: StatePools | None = None, baseline: bool = False,
-                    seed: int = 4):
+                    seed: int = 4, max_batch_bytes: float = 64e6):
     """Poisson arrivals at `rate`; the first `warmup` requests are served but
     not measured.  Returns the summary of the measured requests."""
     import torch
@@ -380,7 +389,8 @@ def serve_benchmark(rate: float, count: int, warmup: int = 200, slots: int = 4, 
         srv = Server(ex, budget, slots=None, max_batch=1, on_complete=release)
     else:
         ex = GpuBatchExecutor(slots)
-        srv = Server(ex, budget, slots=slots, max_batch=max_batch, on_complete=release)
+        srv = Server(ex, budget, slots=slots, max_batch=max_batch, on_complete=release,
+                     max_batch_bytes=max_batch_bytes)
     done = srv.run_arrivals(reqs)
     torch.cuda.synchronize()
     measured = [r for r in done if r.rid >= warmup]
@@ -389,6 +399,7 @@ def serve_benchmark(rate: float, count: int, warmup: int = 200, slots: int = 4, 
     out = summarize(measured)
     out.update({"rate": rate, "launches": srv.launches, "peak_budget_bytes": srv.peak_used,
                 "mode": "one launch per request, FIFO, single stream" if baseline else
-                f"continuous batching, {slots} slots, <= {max_batch} requests per launch"})
+                f"continuous batching, {slots} slots, <= {max_batch} requests and "
+                f"<= {max_batch_bytes / 1e6:g} MB per launch"})
     ex.close()
     return out

@@ -117,6 +117,26 @@ def test_requests_arriving_during_a_batch_start_before_it_ends():
     assert b.t_admit < a.t_done
 
 
+def test_batches_respect_the_byte_cap():
+    clock = VirtualClock()
+    reqs = make_requests(120, 7)
+    cap = 2e6
+    seen = []
+
+    class Recording(FakeExecutor):
+        def launch(self, slot, batch):
+            seen.append(batch)
+            super().launch(slot, batch)
+
+    srv = Server(Recording(clock), 10 ** 12, slots=3, max_batch=16, clock=clock, max_batch_bytes=cap)
+    srv.run_arrivals(reqs)
+    from paper_1809_09851_amd.serve import moved_bytes as mb
+    for b in seen:
+        if len(b) > 1:
+            assert sum(mb(r.op, r.dim, r.n, r.elem) for r in b) <= cap
+    assert len(srv.completed) == 120
+
+
 def test_oversized_request_is_rejected():
     clock = VirtualClock()
     reqs = make_requests(1, 5)
