@@ -226,6 +226,12 @@ typedef struct {
     int64_t ld_out2;
 } fdbb_task;
 
+/* Validate one task as its single-call entry point would (no HIP call). */
+int fdbb_task_check(const fdbb_task *task);
+
+/* Run one task through its single-call entry point on `stream`. */
+int fdbb_task_run(const fdbb_task *task, void *stream);
+
 typedef struct fdbb_batch_plan fdbb_batch_plan;
 
 /* Create a plan for up to `capacity` tasks (>= ntasks) and load `tasks`

@@ -41,12 +41,16 @@ SOURCES = [
     "kernels_batch.hip",
     "kernels_eigen.hip",
     "probes.hip",
+    "fdbb_server.cpp",
 ]
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    # host-only C++ (the server) goes through hipcc as HIP so it sees the
+    # HIP runtime headers; it holds no kernels
+    lang = ["-x", "hip"] if src.endswith(".cpp") else []
+    cmd = [HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")

@@ -569,6 +569,21 @@ int fdbb_char_apply(int dim, int dir, int mode, double gamma, int dtype, const v
     return run(t, stream, mode);
 }
 
+int fdbb_task_check(const fdbb_task *task)
+{
+    if (!task) return fail(FDBB_EINVAL, "task must not be NULL");
+    Call c;
+    int rc = build_call(c, *task);
+    if (!rc) rc = check_alias(c);
+    return rc;
+}
+
+int fdbb_task_run(const fdbb_task *task, void *stream)
+{
+    if (!task) return fail(FDBB_EINVAL, "task must not be NULL");
+    return run(*task, stream);
+}
+
 int fdbb_set_launch_config(int op, int dim, int dtype, int block, int ppt, int grid_cap, int nontemporal)
 {
     if (op < 0 || op >= FDBB_NUM_OPS || dim < 1 || dim > 3 || (dtype != FDBB_F64 && dtype != FDBB_F32))

@@ -54,6 +54,19 @@ class Task(ctypes.Structure):
     ]
 
 
+class Completion(ctypes.Structure):
+    """Mirror of fdbb_completion."""
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("out0", _p), ("out1", _p), ("out2", _p), ("ld", _i64),
+                ("t_submit_ns", _i64), ("t_admit_ns", _i64), ("t_done_ns", _i64)]
+
+
+class ServerStats(ctypes.Structure):
+    """Mirror of fdbb_server_stats."""
+    _fields_ = [("submitted", _i64), ("completed", _i64), ("launches", _i64), ("errors", _i64),
+                ("arena_bytes", _i64), ("peak_arena_bytes", _i64), ("queued", _i64)]
+
+
 _lib = None
 
 
@@ -91,6 +104,14 @@ def library():
         lib.fdbb_batch_exec.argtypes = [_p, _p, _i]
         lib.fdbb_batch_plan_info.argtypes = [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
         lib.fdbb_batch_plan_destroy.argtypes = [_p]
+        lib.fdbb_task_check.argtypes = [ctypes.POINTER(Task)]
+        lib.fdbb_task_run.argtypes = [ctypes.POINTER(Task), _p]
+        lib.fdbb_server_create.argtypes = [_i64, _i, _i, _d, _i, ctypes.POINTER(_p)]
+        lib.fdbb_server_submit.argtypes = [_p, ctypes.POINTER(Task), ctypes.c_uint64]
+        lib.fdbb_server_poll.argtypes = [_p, ctypes.POINTER(Completion), _i, ctypes.POINTER(_i)]
+        lib.fdbb_server_release.argtypes = [_p, ctypes.c_uint64]
+        lib.fdbb_server_get_stats.argtypes = [_p, ctypes.POINTER(ServerStats)]
+        lib.fdbb_server_destroy.argtypes = [_p]
         lib.fdbb_probe_copy.argtypes = [_p, _p, _i64, _i, _p]
         lib.fdbb_probe_write.argtypes = [_p, _i64, ctypes.c_uint64, _i, _p]
         lib.fdbb_probe_read.argtypes = [_p, _i64, _p, _i, _p]

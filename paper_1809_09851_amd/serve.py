@@ -403,3 +403,117 @@ def serve_benchmark(rate: float, count: int, warmup: int = 200, slots: int = 8, 
                 f"<= {max_batch_bytes / 1e6:g} MB per launch"})
     ex.close()
     return out
+
+
+# -------------------------------------------------------------------- native
+class NativeServer:
+    """The C++ server of fdbb_server.h: its scheduler thread batches, launches
+    and retires requests; outputs live in its HBM arena until released."""
+
+    def __init__(self, budget_bytes: int, slots: int = 8, max_batch: int = 64,
+                 max_batch_bytes: float = 64e6, mode: str = "batched"):
+        import ctypes
+
+        import torch
+
+        from . import fdbb as F
+        # the server's streams are not ordered after torch's: inputs written
+        # so far must be complete before requests name them
+        torch.cuda.synchronize()
+        self.F = F
+        self.ct = ctypes
+        self._h = ctypes.c_void_p()
+        code = 0 if mode == "batched" else 1
+        F.check(F.library().fdbb_server_create(int(budget_bytes), slots, max_batch, float(max_batch_bytes),
+                                               code, ctypes.byref(self._h)))
+        self._buf = (F.Completion * 1024)()
+        self._count = ctypes.c_int()
+
+    def submit(self, task, tag: int):
+        self.F.check(self.F.library().fdbb_server_submit(self._h, self.ct.byref(task), tag))
+
+    def poll(self):
+        lib = self.F.library()
+        out = []
+        while True:
+            self.F.check(lib.fdbb_server_poll(self._h, self._buf, len(self._buf), self.ct.byref(self._count)))
+            k = self._count.value
+            out.extend(self._buf[i] for i in range(k))
+            if k < len(self._buf):
+                return out
+
+    def release(self, tag: int):
+        self.F.check(self.F.library().fdbb_server_release(self._h, tag))
+
+    def stats(self) -> dict:
+        st = self.F.ServerStats()
+        self.F.check(self.F.library().fdbb_server_get_stats(self._h, self.ct.byref(st)))
+        return {f: getattr(st, f) for f, _ in st._fields_}
+
+    def close(self):
+        if self._h and self._h.value:
+            self.F.library().fdbb_server_destroy(self._h)
+            self._h = self.ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def request_task(r: Request):
+    """The fdbb_task of a request (outputs are placed by the server)."""
+    from . import batch as B
+    from . import fdbb as F
+    op = r.op
+    t = B._task(op, r.dim, F.dtype_code(r.U.dtype), r.gamma, r.n, -1 if op == "adjoint" else 0)
+    B._set(t, "in0", r.U, r.dim + 2)
+    if op == "adjoint":
+        B._set(t, "in1", r.Fbar, (r.dim + 2) * r.dim)
+    return t
+
+
+def native_serve_benchmark(rate: float, count: int, warmup: int = 200, slots: int = 8, max_batch: int = 64,
+                           budget: int = 200 * 10 ** 9, pools: StatePools | None = None, mode: str = "batched",
+                           seed: int = 4, max_batch_bytes: float = 64e6):
+    """Poisson arrivals at `rate` into the native server; latency runs from
+    each request's scheduled arrival to its completion event (both on the
+    monotonic clock).  The first `warmup` requests are not measured."""
+    import numpy as np
+
+    from . import inputs
+    pools = pools or StatePools()
+    specs = inputs.request_stream(rate, warmup + count, seed=seed, pool=pools.pool)
+    reqs = [pools.request(s) for s in specs]
+    tasks = [request_task(r) for r in reqs]
+    srv = NativeServer(budget, slots=slots, max_batch=max_batch, max_batch_bytes=max_batch_bytes, mode=mode)
+    t0 = time.monotonic_ns() + 2_000_000
+    arrival = [t0 + int(r.t_arrival * 1e9) for r in reqs]
+    done = {}
+    k = 0
+    while len(done) < len(reqs):
+        now = time.monotonic_ns()
+        while k < len(reqs) and arrival[k] <= now:
+            srv.submit(tasks[k], k)
+            k += 1
+        for c in srv.poll():
+            if c.status != 0:
+                raise RuntimeError(f"request {c.tag} failed")
+            done[c.tag] = c.t_done_ns
+            srv.release(c.tag)
+    st = srv.stats()
+    srv.close()
+    ids = range(warmup, warmup + count)
+    lat = np.array([(done[i] - arrival[i]) * 1e-9 for i in ids])
+    span = (max(done[i] for i in ids) - min(arrival[i] for i in ids)) * 1e-9
+    pts = sum(reqs[i].n for i in ids)
+    moved = sum(moved_bytes(reqs[i].op, reqs[i].dim, reqs[i].n, reqs[i].elem) for i in ids)
+    return {"requests": count, "seconds": round(span, 4), "req_s": round(count / span, 1),
+            "gpoints_s": round(pts / span / 1e9, 3), "gb_s": round(moved / span / 1e9, 1),
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4), "rate": rate,
+            "launches": st["launches"], "peak_budget_bytes": st["peak_arena_bytes"],
+            "mode": ("native server, continuous batching, " f"{slots} slots, <= {max_batch} requests and "
+                     f"<= {max_batch_bytes / 1e6:g} MB per launch") if mode == "batched" else
+                    "native server, one launch per request, FIFO, single stream"}

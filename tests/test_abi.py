@@ -117,6 +117,28 @@ def test_eigen_and_char_apply_checks():
     assert lib.fdbb_char_apply(2, 0, 0, 1.4, 0, A0, 128, B0, 128, B0 + 8, 128, 100, None) == F.EALIAS
 
 
+def test_server_rejects_bad_arguments():
+    lib = F.library()
+    h = ctypes.c_void_p()
+    assert lib.fdbb_server_create(0, 4, 64, 1e9, 0, ctypes.byref(h)) == F.EINVAL
+    assert lib.fdbb_server_create(1 << 30, 0, 64, 1e9, 0, ctypes.byref(h)) == F.EINVAL
+    assert lib.fdbb_server_create(1 << 30, 4, 0, 1e9, 0, ctypes.byref(h)) == F.EINVAL
+    assert lib.fdbb_server_create(1 << 30, 4, 64, 0.0, 0, ctypes.byref(h)) == F.EINVAL
+    assert lib.fdbb_server_create(1 << 30, 4, 64, 1e9, 2, ctypes.byref(h)) == F.EINVAL
+    assert not h.value
+
+
+def test_task_check_validates_without_a_gpu():
+    t = F.Task()
+    t.op, t.dim, t.dtype, t.gamma, t.n = 3, 3, 0, 1.4, 100
+    t.in0, t.ld_in0, t.out0, t.ld_out0 = A0, 128, B0, 128
+    assert F.library().fdbb_task_check(ctypes.byref(t)) == F.OK
+    t.out0 = A0 + 8
+    assert F.library().fdbb_task_check(ctypes.byref(t)) == F.EALIAS
+    t.dim = 5
+    assert F.library().fdbb_task_check(ctypes.byref(t)) == F.EINVAL
+
+
 def test_launch_config_table():
     lib = F.library()
     assert lib.fdbb_set_launch_config(3, 3, 0, 100, 1, 0, 1) == F.EINVAL   # not a multiple of 64

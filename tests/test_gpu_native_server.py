@@ -1,0 +1,119 @@
+"""The native server (fdbb_server.h): requests batched by its scheduler
+thread into its HBM arena match the oracle, equal the one-launch-per-request
+mode, respect the budget, and give their memory back on release."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import GAMMA, host, require_gpu
+from metrics import TOL, blocks_error, flux_groups, group_error, state_groups
+import oracle
+from paper_1809_09851_amd import fdbb as F
+from paper_1809_09851_amd import inputs
+from paper_1809_09851_amd import serve as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pools():
+    require_gpu()
+    return S.StatePools(pool=200_000, seed=5)
+
+
+def _requests(pools, count, seed):
+    specs = inputs.request_stream(1e5, count, seed=seed, pool=200_000, lo_exp=2.0, hi_exp=5.2)
+    return [pools.request(s) for s in specs]
+
+
+def _fetch(r, c):
+    """Copy a completion's first output out of the arena into a tensor."""
+    dtype = torch.float64 if r.elem == 8 else torch.float32
+    K = r.dim + 2
+    kind, count = S.out_shape(r.op, r.dim, r.n)
+    if kind == "fields":
+        t = torch.empty((count, c.ld), dtype=dtype, device="cuda")
+    else:
+        t = torch.empty((r.dim, c.ld, K, K), dtype=dtype, device="cuda")
+    F.check(F.library().fdbb_probe_copy(c.out0, t.data_ptr(), t.numel() * t.element_size(), 0, None))
+    torch.cuda.synchronize()
+    return t[:, :r.n]
+
+
+def _run(srv, reqs, release=True):
+    tasks = [S.request_task(r) for r in reqs]
+    for k, t in enumerate(tasks):
+        srv.submit(t, k)
+    out = {}
+    t_end = time.time() + 60
+    while len(out) < len(reqs):
+        for c in srv.poll():
+            assert c.status == 0
+            out[c.tag] = _fetch(reqs[c.tag], c)
+            if release:
+                srv.release(c.tag)
+        assert time.time() < t_end, "server did not finish"
+    return out
+
+
+def _check(r, got):
+    dt = "f64" if r.elem == 8 else "f32"
+    Uo = host(r.U)
+    if r.op == "cons2prim":
+        assert group_error(host(got), oracle.cons2prim(r.dim, GAMMA, Uo), state_groups(r.dim)) <= TOL[dt]
+    elif r.op == "flux":
+        assert group_error(host(got), oracle.flux(r.dim, GAMMA, Uo), flux_groups(r.dim)) <= TOL[dt]
+    elif r.op == "flux_jacobian":
+        assert blocks_error(host(got), oracle.flux_jacobian(r.dim, GAMMA, Uo)) <= TOL[dt]
+    else:
+        Fb = host(r.Fbar)
+        K = r.dim + 2
+        A = np.abs(oracle.flux_jacobian(r.dim, GAMMA, Uo))
+        den = np.zeros((K, r.n))
+        for d in range(r.dim):
+            den += np.einsum("nrc,rn->cn", A[d], np.abs(np.array([Fb[q * r.dim + d] for q in range(K)])))
+        ref = oracle.flux_adjoint(r.dim, -1, GAMMA, Uo, Fb)
+        assert group_error(host(got), ref, [list(range(K))], denom=den.max(axis=0)) <= TOL[dt]
+
+
+def test_batched_results_match_oracle_and_single_mode(pools):
+    reqs = _requests(pools, 40, 21)
+    srv = S.NativeServer(8 * 10 ** 9, slots=3, max_batch=16, max_batch_bytes=1e12, mode="batched")
+    batched = _run(srv, reqs)
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == 40 and st["launches"] < 40 and st["arena_bytes"] == 0
+    single = S.NativeServer(8 * 10 ** 9, slots=4, mode="single")
+    alone = _run(single, reqs)
+    single.close()
+    for k, r in enumerate(reqs):
+        _check(r, batched[k])
+        tol = 1e-14 if r.elem == 8 else 1.2e-7
+        a, b = host(alone[k]), host(batched[k])
+        den = np.maximum(np.abs(b).max(), 1e-300)
+        assert np.max(np.abs(a - b)) / den <= tol
+
+
+def test_budget_holds_and_memory_returns(pools):
+    reqs = _requests(pools, 30, 22)
+    need = max(r.out_bytes for r in reqs)
+    budget = 3 * need
+    srv = S.NativeServer(budget, slots=4, max_batch=8, max_batch_bytes=1e12)
+    _run(srv, reqs)
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == 30
+    assert st["peak_arena_bytes"] <= budget + 4096
+    assert st["arena_bytes"] == 0
+
+
+def test_oversized_request_is_refused(pools):
+    reqs = _requests(pools, 1, 23)
+    srv = S.NativeServer(1 << 20, slots=1)
+    big = reqs[0]
+    if big.out_bytes > (1 << 20):
+        with pytest.raises(F.FdbbError):
+            srv.submit(S.request_task(big), 0)
+    srv.close()
