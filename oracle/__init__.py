@@ -20,6 +20,8 @@ Sections cited below are those of the FDBB paper:
   * flux_adjoint                -- transpose of the flux Jacobians
   * eigenvectors, char_apply    -- characteristic decomposition of A_d (Fig. 1,
                                    "characteristic variables", linearised)
+  * roe_average                 -- Roe's averaged state between two states, the
+                                   linearisation point of that decomposition
 """
 from __future__ import annotations
 
@@ -95,6 +97,8 @@ class Oracle:
         lib.oracle_eigenvectors.restype = _int
         lib.oracle_char_apply.argtypes = [_int, _int, _int, _dbl, _dp, _i64, _dp, _i64, _dp, _i64, _i64]
         lib.oracle_char_apply.restype = _int
+        lib.oracle_roe_average.argtypes = [_int, _dbl, _dp, _i64, _dp, _i64, _dp, _i64, _i64]
+        lib.oracle_roe_average.restype = _int
         self.lib = lib
         self.path = path
 
@@ -210,6 +214,17 @@ class Oracle:
         _check(rc)
         return Y
 
+    def roe_average(self, dim, gamma, UL, UR):
+        """Roe-averaged conservative state between UL and UR, shape (K, n)."""
+        UL = _soa(UL, dim + 2)
+        UR = _soa(UR, dim + 2)
+        if UL.shape != UR.shape:
+            raise ValueError("UL and UR differ in shape")
+        n = UL.shape[1]
+        Uh = np.empty_like(UL)
+        _check(self.lib.oracle_roe_average(dim, gamma, _ptr(UL), n, _ptr(UR), n, _ptr(Uh), n, n))
+        return Uh
+
     def fused(self, dim, gamma, U):
         """The fused pass is, by definition, the flux, the flux Jacobians and
         the Riemann invariants of the same state."""
@@ -279,3 +294,7 @@ def eigenvectors(dim, gamma, U):
 
 def char_apply(dim, direction, mode, gamma, U, X):
     return default().char_apply(dim, direction, mode, gamma, U, X)
+
+
+def roe_average(dim, gamma, UL, UR):
+    return default().roe_average(dim, gamma, UL, UR)

@@ -518,3 +518,41 @@ int oracle_char_apply(int dim, int dir, int mode, double gamma, const double *U,
     }
     return 0;
 }
+
+/* Roe-averaged state between a left and a right state (the linearisation
+ * point of the characteristic decomposition between two states; Roe's
+ * average for the perfect gas).  With weights a = sqrt(rho_L), b =
+ * sqrt(rho_R):
+ *   rho^ = a b,   v^ = (a v_L + b v_R) / (a + b),
+ *   H^   = (a H_L + b H_R) / (a + b),  H = (E + p) / rho,
+ * returned as the conservative state with that density, velocity and total
+ * enthalpy: m^ = rho^ v^, and, since H = gamma p / ((gamma-1) rho) + |v|^2/2,
+ *   p^ = (gamma-1)/gamma * rho^ (H^ - |v^|^2/2),   E^ = rho^ H^ - p^. */
+int oracle_roe_average(int dim, double gamma, const double *UL, int64_t ldL,
+                       const double *UR, int64_t ldR, double *Uh, int64_t ldH, int64_t n)
+{
+    int64_t i;
+    int k;
+    if (!dim_ok(dim))
+        return -1;
+    for (i = 0; i < n; ++i) {
+        point_state l = load_cons(dim, gamma, UL, ldL, i);
+        point_state r = load_cons(dim, gamma, UR, ldR, i);
+        double a = sqrt(l.rho), b = sqrt(r.rho);
+        double HL = (l.E + l.p) / l.rho, HR = (r.E + r.p) / r.rho;
+        double rho = a * b;
+        double H = (a * HL + b * HR) / (a + b);
+        double q = 0.0, p;
+        double v[3];
+        for (k = 0; k < dim; ++k) {
+            v[k] = (a * l.v[k] + b * r.v[k]) / (a + b);
+            q = q + v[k] * v[k];
+        }
+        p = (gamma - 1.0) / gamma * rho * (H - 0.5 * q);
+        Uh[0 * ldH + i] = rho;
+        for (k = 0; k < dim; ++k)
+            Uh[(1 + k) * ldH + i] = rho * v[k];
+        Uh[(dim + 1) * ldH + i] = rho * H - p;
+    }
+    return 0;
+}

@@ -503,6 +503,74 @@ def pin_characteristic_decomposition(o):
                 close(o.char_apply(dim, d, 1, g, U, YL), X, 1e-12, "R L = I")
 
 
+def _state_pairs(dim, n, seed, gamma):
+    """Two independent thermal states per point, built without the oracle."""
+    UL = thermal_state(dim, n, seed, gamma)[0]
+    UR = thermal_state(dim, n, seed + 1000, gamma)[0]
+    # a few pairs far apart: strong density and temperature jumps
+    UR[:, : n // 4] *= np.linspace(0.05, 20.0, n // 4)[None]
+    return UL, UR
+
+
+def pin_roe_property(o):
+    """Roe's defining property: the Jacobian at the averaged state maps the
+    jump in state onto the jump in flux exactly, A_d(U^)(U_R - U_L) =
+    F_d(U_R) - F_d(U_L), for every direction d.  This fixes the averaged
+    velocity and total enthalpy."""
+    for g in GAMMAS:
+        for dim in (1, 2, 3):
+            UL, UR = _state_pairs(dim, 64, 40 + dim, g)
+            Uh = o.roe_average(dim, g, UL, UR)
+            A = o.flux_jacobian(dim, g, Uh)
+            dF = o.flux(dim, g, UR) - o.flux(dim, g, UL)
+            dU = UR - UL
+            for d in range(dim):
+                lhs = np.einsum("nrc,cn->rn", A[d], dU)
+                rhs = dF[[r * dim + d for r in range(dim + 2)]]
+                for i in range(dU.shape[1]):
+                    close(lhs[:, i], rhs[:, i], 1e-12, f"Roe property {dim}D d={d}",
+                          scale=np.abs(A[d, i]).max() * np.abs(dU[:, i]).max())
+
+
+def pin_roe_product_rule(o):
+    """The averaged density makes the discrete product rule exact for the
+    momentum: (rho v)_R - (rho v)_L = rho^ (v_R - v_L) + v^ (rho_R - rho_L)
+    (v^ is pinned by the Roe property), which fixes rho^ = sqrt(rho_L rho_R)
+    without restating it."""
+    for g in GAMMAS:
+        for dim in (1, 2, 3):
+            UL, UR = _state_pairs(dim, 64, 50 + dim, g)
+            Uh = o.roe_average(dim, g, UL, UR)
+            rho = Uh[0]
+            v = Uh[1:dim + 1] / rho
+            vL = UL[1:dim + 1] / UL[0]
+            vR = UR[1:dim + 1] / UR[0]
+            for k in range(dim):
+                lhs = UR[1 + k] - UL[1 + k]
+                rhs = rho * (vR[k] - vL[k]) + v[k] * (UR[0] - UL[0])
+                scale = np.abs(UR[1 + k]) + np.abs(UL[1 + k])
+                close(lhs / scale, rhs / scale, 1e-12, f"product rule {dim}D k={k}", scale=1.0)
+
+
+def pin_roe_consistency(o):
+    """Between a state and itself the average is that state; the average
+    does not depend on which state is called left; and in the sound speed
+    of the averaged state, c^2 = (gamma-1)(H^ - |v^|^2/2), lies between the
+    limits set by the two states' enthalpies (H^ is a convex combination)."""
+    for g in GAMMAS:
+        for dim in (1, 2, 3):
+            UL, UR = _state_pairs(dim, 64, 60 + dim, g)
+            close(o.roe_average(dim, g, UL, UL), UL, 1e-14, "average of equal states")
+            close(o.roe_average(dim, g, UL, UR), o.roe_average(dim, g, UR, UL), 1e-15, "symmetry")
+            Uh = o.roe_average(dim, g, UL, UR)
+            p = o.eos(dim, g, Uh)[0]
+            H = (Uh[-1] + p) / Uh[0]
+            HL = (UL[-1] + o.eos(dim, g, UL)[0]) / UL[0]
+            HR = (UR[-1] + o.eos(dim, g, UR)[0]) / UR[0]
+            lo, hi = np.minimum(HL, HR), np.maximum(HL, HR)
+            assert np.all(H >= lo * (1 - 1e-14)) and np.all(H <= hi * (1 + 1e-14)), "H^ outside [H_L, H_R]"
+
+
 PINS = [
     pin_worked_state,
     pin_v_mag2,
@@ -523,4 +591,7 @@ PINS = [
     pin_characteristic_transform,
     pin_adjoint_fd,
     pin_characteristic_decomposition,
+    pin_roe_property,
+    pin_roe_product_rule,
+    pin_roe_consistency,
 ]

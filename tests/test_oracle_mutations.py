@@ -50,6 +50,18 @@ MUTATIONS = [
     ("adjoint cotangent layout", "int64_t field = (dir >= 0) ? r : (r * dim + d);",
      "int64_t field = (dir >= 0) ? r : (d * (dim + 2) + r);"),
 ]
+MUTATIONS += [
+    ("Roe velocity plain mean", "v[k] = (a * l.v[k] + b * r.v[k]) / (a + b);",
+     "v[k] = 0.5 * (l.v[k] + r.v[k]);"),
+    ("Roe velocity weights swapped", "v[k] = (a * l.v[k] + b * r.v[k]) / (a + b);",
+     "v[k] = (b * l.v[k] + a * r.v[k]) / (a + b);"),
+    ("Roe density plain mean", "double rho = a * b;", "double rho = 0.5 * (l.rho + r.rho);"),
+    ("Roe enthalpy from left only", "double H = (a * HL + b * HR) / (a + b);", "double H = HL;"),
+    ("Roe enthalpy without pressure", "double HL = (l.E + l.p) / l.rho,", "double HL = l.E / l.rho,"),
+    ("Roe pressure factor", "p = (gamma - 1.0) / gamma * rho * (H - 0.5 * q);",
+     "p = (gamma - 1.0) * rho * (H - 0.5 * q);"),
+    ("Roe energy sign", "Uh[(dim + 1) * ldH + i] = rho * H - p;", "Uh[(dim + 1) * ldH + i] = rho * H + p;"),
+]
 MUTATIONS = [m for m in MUTATIONS if m[2] is not None]
 
 
