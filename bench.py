@@ -254,20 +254,30 @@ def bench_autograd(steps: int, warmup: int):
     return {"n": n, "ms_per_fwd_bwd": round(wall, 4), "gpoints_s": round(n / (wall * 1e-3) / 1e9, 3)}
 
 
-def bench_serving(rates, count: int, warmup: int, slots: int = 8, batch_mb: float = 64.0):
+def bench_serving(rates, count: int, warmup: int, slots: int = 8, batch_mb: float = 64.0,
+                  engine: str = "native", budget: int = 64 * 10 ** 9):
     """Poisson request streams: continuous batching against one launch per
-    request on a single stream (same requests, same pools)."""
+    request on a single stream (same requests, same pools), through the
+    native server, the Python scheduler, or both."""
     from paper_1809_09851_amd import serve as S
     pools = S.StatePools()
     out = []
+    engines = ("native", "python") if engine == "both" else (engine,)
     for rate in rates:
-        for baseline in (False, True):
-            r = S.serve_benchmark(rate, count, warmup=warmup, pools=pools, baseline=baseline, slots=slots,
-                                  max_batch_bytes=batch_mb * 1e6)
-            print(f"# serving rate={rate:g} {'baseline' if baseline else 'batched'}: "
-                  f"p50 {r['p50_ms']} ms p99 {r['p99_ms']} ms, {r['req_s']} req/s",
-                  file=sys.stderr, flush=True)
-            out.append(r)
+        for eng in engines:
+            for baseline in (False, True):
+                if eng == "native":
+                    r = S.native_serve_benchmark(rate, count, warmup=warmup, pools=pools, slots=slots,
+                                                 mode="single" if baseline else "batched", budget=budget,
+                                                 max_batch_bytes=batch_mb * 1e6)
+                else:
+                    r = S.serve_benchmark(rate, count, warmup=warmup, pools=pools, baseline=baseline,
+                                          slots=slots, budget=budget, max_batch_bytes=batch_mb * 1e6)
+                r["engine"] = eng
+                print(f"# serving {eng} rate={rate:g} {'baseline' if baseline else 'batched'}: "
+                      f"p50 {r['p50_ms']} ms p99 {r['p99_ms']} ms, {r['req_s']} req/s",
+                      file=sys.stderr, flush=True)
+                out.append(r)
     del pools
     return out
 
@@ -367,6 +377,31 @@ def bench_paper_sweeps(steps: int = 20, warmup: int = 3, lo: int = 10, hi: int =
     return rows
 
 
+def bench_ops(steps: int, warmup: int, dims=(3,), dtypes=("f64", "f32")):
+    """Every single-op entry point on its own, at a size whose working set is
+    about 2 GB (far above the 256 MB last-level cache): ms per launch and
+    algorithmic GB/s against the HBM peak."""
+    import torch
+    from paper_1809_09851_amd import tune
+    out = {}
+    ops = ("cons2prim", "prim2cons", "eos", "v_mag2", "flux", "flux_jacobian", "riemann_invariants",
+           "cons2char", "char2cons", "adjoint", "eigenvectors", "char_apply", "roe_average")
+    for dim in dims:
+        for dt in dtypes:
+            dtype = torch.float64 if dt == "f64" else torch.float32
+            es = 8 if dt == "f64" else 4
+            for op in ops:
+                n = tune.auto_size(op, dim, es)
+                fn = tune.workload(op, dim, dtype, n)
+                _, ev = timed_launches(fn, steps, warmup)
+                gbs = tune.bytes_per_point(op, dim, es) * n / (ev * 1e-3) / 1e9
+                out[f"{op}/{dim}d/{dt}"] = {"n": n, "kernel_ms": round(ev, 4), "achieved_gbs": round(gbs, 1),
+                                            "frac": round(gbs / HBM_PEAK_GBS, 4)}
+                del fn
+                torch.cuda.empty_cache()
+    return out
+
+
 def bench_probes(steps: int, warmup: int, gib: float = 4.0):
     """What HBM delivers to plain streaming kernels: read, write, copy."""
     import torch
@@ -399,6 +434,8 @@ def main(argv=None):
     ap.add_argument("--serve-count", type=int, default=1000)
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-engine", choices=("native", "python", "both"), default="native",
+                    help="the C++ server (fdbb_server.h), the Python scheduler, or both")
     ap.add_argument("--serve-batch-mb", type=float, default=64.0,
                     help="HBM megabytes one batched launch may move")
     ap.add_argument("--paper-sweeps", action="store_true",
@@ -460,13 +497,14 @@ def main(argv=None):
         ex["batched_512_f64"] = bench_batched(5, 2, torch.float64)
         ex["batched_512_f32"] = bench_batched(5, 2, torch.float32)
         ex["hbm_probes_gbs"] = bench_probes(max(10, args.steps // 5), 3)
+        ex["single_ops_2gb"] = bench_ops(max(10, args.steps // 5), 3)
         line["extras"] = ex
     if args.paper_sweeps:
         line["paper_sweeps"] = bench_paper_sweeps()
     rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
     if rates:
         line["serving"] = bench_serving(rates, args.serve_count, args.serve_warmup, args.serve_slots,
-                                        args.serve_batch_mb)
+                                        args.serve_batch_mb, args.serve_engine)
     if args.probe_copy:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
         b = torch.empty_like(a)

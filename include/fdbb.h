@@ -85,7 +85,8 @@ typedef enum {
     FDBB_OP_V_MAG2 = 10,
     FDBB_OP_EIGENVECTORS = 11,
     FDBB_OP_CHAR_APPLY = 12,
-    FDBB_NUM_OPS = 13
+    FDBB_OP_ROE_AVERAGE = 13,
+    FDBB_NUM_OPS = 14
 } fdbb_op;
 
 /* Conservative -> primitive (Sec. 2.2, "Variables", conversion figure):
@@ -178,6 +179,19 @@ int fdbb_eigenvectors(int dim, double gamma, int dtype, const void *U, int64_t l
  * Y == X (same ld) works in place.  Not available as a batch task. */
 int fdbb_char_apply(int dim, int dir, int mode, double gamma, int dtype, const void *U, int64_t ldU,
                     const void *X, int64_t ldX, void *Y, int64_t ldY, int64_t n, void *stream);
+
+/* Roe-averaged state between a left state UL and a right state UR, the
+ * point at which the characteristic decomposition between two states is
+ * linearised (Fig. 1, "characteristic variables"; Roe's average for the
+ * perfect gas): with a = sqrt(rho_L), b = sqrt(rho_R), rho^ = a b, v^ and
+ * H^ = (E + p)/rho averaged with weights a and b, written as the conservative
+ * state Uh = (rho^, rho^ v^, rho^ H^ - p^), p^ = (gamma-1)/gamma rho^ (H^ -
+ * |v^|^2/2).  The Jacobians at Uh satisfy A_d(Uh)(UR - UL) = F_d(UR) -
+ * F_d(UL); fdbb_eigenvectors and fdbb_char_apply take Uh as their state.
+ * UL, UR and Uh have K fields each; Uh may be UL or UR (same base and ld:
+ * in place).  Also a batch task (in0 = UL, in1 = UR, out0 = Uh). */
+int fdbb_roe_average(int dim, double gamma, int dtype, const void *UL, int64_t ldUL, const void *UR,
+                     int64_t ldUR, void *Uh, int64_t ldUh, int64_t n, void *stream);
 
 /* ---------------------------------------------------------------- tuning
  * Launch configuration per (op, dim, dtype): `block` threads per workgroup

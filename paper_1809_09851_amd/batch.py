@@ -81,6 +81,15 @@ def adjoint_task(U, Fbar, Ubar, gamma=1.4, direction=-1):
     return t
 
 
+def roe_task(UL, UR, Uh, gamma=1.4):
+    dim = UL.shape[0] - 2
+    t = _task("roe_average", dim, F.dtype_code(UL.dtype), gamma, UL.shape[1])
+    _set(t, "in0", UL, dim + 2)
+    _set(t, "in1", UR, dim + 2)
+    _set(t, "out0", Uh, dim + 2)
+    return t
+
+
 def riemann_task(U, R, gamma=1.4):
     dim = U.shape[0] - 2
     t = _task("riemann_invariants", dim, F.dtype_code(U.dtype), gamma, U.shape[1])

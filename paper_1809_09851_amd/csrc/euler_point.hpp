@@ -254,4 +254,28 @@ __device__ __forceinline__ void adjoint_accumulate(const Gas &g, const State<D> 
     ubar[D + 1] += g.g1 * bd + g.gamma * vd * e;
 }
 
+// Roe-averaged state between a left and a right state, as a conservative
+// state: with a = sqrt(rho_L), b = sqrt(rho_R), rho^ = a b and the velocity
+// and total enthalpy H = (E + p) / rho averaged with weights a and b; the
+// pressure follows from H^ = gamma p^ / ((gamma - 1) rho^) + |v^|^2 / 2.
+// The flux Jacobians at this state satisfy A(U^)(U_R - U_L) = F(U_R) - F(U_L).
+template <int D>
+__device__ __forceinline__ void roe_average(const Gas &g, const State<D> &l, const State<D> &r, double *out)
+{
+    const double a = sqrt(l.rho), b = sqrt(r.rho);
+    const double w = 1.0 / (a + b);
+    const double rho = a * b;
+    const double H = (a * (l.E + l.p) * l.rinv + b * (r.E + r.p) * r.rinv) * w;
+    double q = 0.0;
+    out[0] = rho;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double v = (a * l.v[k] + b * r.v[k]) * w;
+        q += v * v;
+        out[1 + k] = rho * v;
+    }
+    const double p = g.g1 * g.inv_gamma * rho * (H - 0.5 * q);
+    out[D + 1] = rho * H - p;
+}
+
 }  // namespace fdbb

@@ -225,6 +225,41 @@ __device__ __forceinline__ void tile_prim2cons(const Args &a, int64_t tile0)
     }
 }
 
+// Roe-averaged state between the states in in0 (left) and in1 (right).
+template <int D, typename T, int P, bool NT>
+__device__ __forceinline__ void tile_roe(const Args &a, int64_t tile0)
+{
+    constexpr int K = D + 2;
+    using L_t = Lane<T, P, NT>;
+    constexpr int W = L_t::W, NC = L_t::NC;
+    const L_t L(a, tile0);
+    if (!L.any()) return;
+    double ul[NC][K][W], ur[NC][K][W];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        L.template load_fields<K>(a.in0, a.ld_in0, c, ul[c]);
+        L.template load_fields<K>(a.in1, a.ld_in1, c, ur[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double out[K][W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            double lj[K], rj[K], hj[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                lj[k] = ul[c][k][j];
+                rj[k] = ur[c][k][j];
+            }
+            roe_average<D>(a.gas, make_state<D>(a.gas, lj), make_state<D>(a.gas, rj), hj);
+#pragma unroll
+            for (int k = 0; k < K; ++k) out[k][j] = hj[k];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) L.store(a.out0, a.ld_out0, k, c, out[k]);
+    }
+}
+
 template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void tile_vmag2(const Args &a, int64_t tile0)
 {

@@ -240,6 +240,7 @@ int family_of(int op)
     case FDBB_OP_V_MAG2: return kFamVmag2;
     case FDBB_OP_EIGENVECTORS: return kFamEigen;
     case FDBB_OP_CHAR_APPLY: return kFamCharApply;
+    case FDBB_OP_ROE_AVERAGE: return kFamRoe;
     default: return -1;
     }
 }
@@ -253,7 +254,8 @@ const void *kernel_for(int op, int dim, int dtype, int ppt, bool nt)
     case kFamEos:
     case kFamFlux:
     case kFamRiemann:
-    case kFamVmag2: return kernel_pointwise(fam, dim, dtype, ppt, nt);
+    case kFamVmag2:
+    case kFamRoe: return kernel_pointwise(fam, dim, dtype, ppt, nt);
     case kFamCons2Char:
     case kFamChar2Cons: return kernel_char(fam, dim, dtype, ppt, nt);
     case kFamFused: return kernel_fused(dim, dtype, ppt, nt);
@@ -390,6 +392,14 @@ int build_call(Call &c, const fdbb_task &t, int mode = 0)
         if ((rc = add_fields(c, t.in0, t.ld_in0, K, 1, true, true, "U"))) return rc;
         if ((rc = add_fields(c, t.in1, t.ld_in1, K, 1, true, true, "X"))) return rc;
         if ((rc = add_fields(c, t.out0, t.ld_out0, K, 1, false, true, "Y"))) return rc;
+        break;
+    case FDBB_OP_ROE_AVERAGE:
+        c.inplace_ok = true;
+        a.in0 = t.in0, a.ld_in0 = t.ld_in0, a.in1 = t.in1, a.ld_in1 = t.ld_in1;
+        a.out0 = t.out0, a.ld_out0 = t.ld_out0;
+        if ((rc = add_fields(c, t.in0, t.ld_in0, K, 1, true, true, "UL"))) return rc;
+        if ((rc = add_fields(c, t.in1, t.ld_in1, K, 1, true, true, "UR"))) return rc;
+        if ((rc = add_fields(c, t.out0, t.ld_out0, K, 1, false, true, "Uh"))) return rc;
         break;
     case FDBB_OP_V_MAG2:
         a.in0 = t.in0, a.ld_in0 = t.ld_in0, a.out0 = t.out0;
@@ -567,6 +577,14 @@ int fdbb_char_apply(int dim, int dir, int mode, double gamma, int dtype, const v
     fdbb_task t = make_task(FDBB_OP_CHAR_APPLY, dim, dir, gamma, dtype, n);
     t.in0 = U, t.ld_in0 = ldU, t.in1 = X, t.ld_in1 = ldX, t.out0 = Y, t.ld_out0 = ldY;
     return run(t, stream, mode);
+}
+
+int fdbb_roe_average(int dim, double gamma, int dtype, const void *UL, int64_t ldUL, const void *UR,
+                     int64_t ldUR, void *Uh, int64_t ldUh, int64_t n, void *stream)
+{
+    fdbb_task t = make_task(FDBB_OP_ROE_AVERAGE, dim, 0, gamma, dtype, n);
+    t.in0 = UL, t.ld_in0 = ldUL, t.in1 = UR, t.ld_in1 = ldUR, t.out0 = Uh, t.ld_out0 = ldUh;
+    return run(t, stream);
 }
 
 int fdbb_task_check(const fdbb_task *task)

@@ -41,6 +41,7 @@ enum Family : int {
     kFamVmag2,
     kFamEigen,      // eigenvector blocks (staged like the Jacobian)
     kFamCharApply,  // products with L or R of one direction
+    kFamRoe,        // Roe-averaged state of two states
     kNumFamilies
 };
 

@@ -7,6 +7,7 @@
 #include "../../include/fdbb_server.h"
 
 #include <hip/hip_runtime.h>
+#include <sys/prctl.h>
 
 #include <algorithm>
 #include <atomic>
@@ -33,6 +34,10 @@ int64_t now_ns()
         .count();
 }
 
+// After its last activity the scheduler polls for this long before it
+// sleeps, so that a request arriving soon after is picked up at once.
+constexpr int64_t kSpinNs = 200000;
+
 size_t elem_size(int dtype) { return dtype == FDBB_F64 ? 8 : 4; }
 
 // Output layout of a task: sizes in elements of each output slot, and the
@@ -53,7 +58,8 @@ bool out_shape(const fdbb_task &t, OutShape *s)
     case FDBB_OP_PRIM2CONS:
     case FDBB_OP_CONS2CHAR:
     case FDBB_OP_CHAR2CONS:
-    case FDBB_OP_ADJOINT: s->bytes[0] = (size_t)(K * ld) * es; return true;
+    case FDBB_OP_ADJOINT:
+    case FDBB_OP_ROE_AVERAGE: s->bytes[0] = (size_t)(K * ld) * es; return true;
     case FDBB_OP_FLUX: s->bytes[0] = (size_t)(K * D * ld) * es; return true;
     case FDBB_OP_RIEMANN: s->bytes[0] = (size_t)((2 * D + 1) * ld) * es; return true;
     case FDBB_OP_FLUX_JACOBIAN: s->bytes[0] = (size_t)(D * ld * K * K) * es; return true;
@@ -82,6 +88,7 @@ double moved_bytes(const fdbb_task &t)
     case FDBB_OP_CONS2CHAR:
     case FDBB_OP_CHAR2CONS: per = 2 * K; break;
     case FDBB_OP_ADJOINT: per = K * K; break;
+    case FDBB_OP_ROE_AVERAGE: per = 3 * K; break;
     case FDBB_OP_FLUX: per = K + K * D; break;
     case FDBB_OP_RIEMANN: per = K + 2 * D + 1; break;
     case FDBB_OP_FLUX_JACOBIAN: per = K + D * K * K; break;
@@ -189,6 +196,7 @@ struct fdbb_server {
     std::unordered_map<uint64_t, Request> outstanding;  // completed, not yet released
     std::unordered_set<uint64_t> live;                  // tags submitted, not yet released
     fdbb_server_stats stats{};
+    bool kick = false;  // set by submit and release: wakes a sleeping scheduler
     std::atomic<bool> stop{false};
     std::thread worker;
     std::string error;
@@ -261,13 +269,19 @@ int launch(fdbb_server *s, Slot &slot)
 void run_loop(fdbb_server *s)
 {
     (void)hipSetDevice(s->device);
+    // sleeps below are short; ask for them to be honoured to the microsecond
+    (void)prctl(PR_SET_TIMERSLACK, 1UL, 0UL, 0UL, 0UL);
+    int64_t last_active = now_ns();
     while (!s->stop.load(std::memory_order_relaxed)) {
-        bool progressed = false;
+        bool progressed = false, any_busy = false;
         // retire finished slots
         for (Slot &slot : s->slots) {
             if (!slot.busy) continue;
             const hipError_t q = hipEventQuery(slot.done);
-            if (q == hipErrorNotReady) continue;
+            if (q == hipErrorNotReady) {
+                any_busy = true;
+                continue;
+            }
             const int64_t t = now_ns();
             std::lock_guard<std::mutex> lock(s->mu);
             for (Request &r : slot.batch) {
@@ -303,14 +317,26 @@ void run_loop(fdbb_server *s)
                 s->stats.errors += 1;
             }
             slot.busy = true;  // the event (or its failure) retires the batch
+            any_busy = true;
             progressed = true;
         }
-        if (!progressed) {
-            std::unique_lock<std::mutex> lock(s->mu);
-            // nothing to admit and nothing finished: wait briefly for a
-            // submission or a release (busy slots are polled every 20 us)
-            s->cv.wait_for(lock, std::chrono::microseconds(20));
+        const int64_t now = now_ns();
+        if (progressed || any_busy) {
+            // launches in flight: poll their events without sleeping
+            if (progressed) last_active = now;
+            std::this_thread::yield();
+            continue;
         }
+        if (now - last_active < kSpinNs) {
+            // recently active: a next arrival is likely soon
+            std::this_thread::yield();
+            continue;
+        }
+        // idle, or the queue head waits for memory: sleep until a
+        // submission or a release (both notify), re-checking now and then
+        std::unique_lock<std::mutex> lock(s->mu);
+        s->cv.wait_for(lock, std::chrono::microseconds(500), [s] { return s->kick || s->stop.load(); });
+        s->kick = false;
     }
 }
 
@@ -393,6 +419,7 @@ int fdbb_server_submit(fdbb_server *s, const fdbb_task *task, uint64_t tag)
         if (!s->live.insert(tag).second) return FDBB_EINVAL;
         s->queue.push_back(r);
         s->stats.submitted += 1;
+        s->kick = true;
     }
     s->cv.notify_one();
     return FDBB_OK;
@@ -422,6 +449,7 @@ int fdbb_server_release(fdbb_server *s, uint64_t tag)
             if (it->second.bytes[k]) s->arena.free(it->second.off[k], it->second.bytes[k]);
         s->outstanding.erase(it);
         s->live.erase(tag);
+        s->kick = true;
     }
     s->cv.notify_one();
     return FDBB_OK;

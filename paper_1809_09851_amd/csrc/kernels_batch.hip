@@ -22,6 +22,7 @@ __device__ __forceinline__ void run_tile(int op, const Args &a, int64_t tile0, u
     case 7: tile_char2cons<D, T, P, NT>(a, tile0); break;
     case 9: tile_adjoint<D, T, P, NT>(a, tile0); break;
     case 10: tile_vmag2<D, T, P, NT>(a, tile0); break;
+    case 13: tile_roe<D, T, P, NT>(a, tile0); break;
     default: break;
     }
 }

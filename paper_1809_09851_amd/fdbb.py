@@ -27,7 +27,7 @@ OK, EINVAL, EALIGN, EALIAS, EHIP, ENOMEM = range(6)
 OPS = {
     "cons2prim": 0, "prim2cons": 1, "eos": 2, "flux": 3, "flux_jacobian": 4,
     "riemann_invariants": 5, "cons2char": 6, "char2cons": 7, "fused": 8, "adjoint": 9,
-    "v_mag2": 10, "eigenvectors": 11, "char_apply": 12,
+    "v_mag2": 10, "eigenvectors": 11, "char_apply": 12, "roe_average": 13,
 }
 ROW_ALIGN = 64  # elements; keeps every row 16-byte aligned for both dtypes
 
@@ -89,6 +89,7 @@ def library():
         lib.fdbb_flux_adjoint.argtypes = [_i, _i, _d, _i, _p, _i64, _p, _i64, _p, _i64, _i64, _p]
         lib.fdbb_eigenvectors.argtypes = [_i, _d, _i, _p, _i64, _p, _i64, _p, _i64, _i64, _p]
         lib.fdbb_char_apply.argtypes = [_i, _i, _i, _d, _i, _p, _i64, _p, _i64, _p, _i64, _i64, _p]
+        lib.fdbb_roe_average.argtypes = [_i, _d, _i, _p, _i64, _p, _i64, _p, _i64, _i64, _p]
         lib.fdbb_set_launch_config.argtypes = [_i, _i, _i, _i, _i, _i, _i]
         lib.fdbb_get_launch_config.argtypes = [_i, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i),
                                                ctypes.POINTER(_i), ctypes.POINTER(_i)]
@@ -309,6 +310,15 @@ def fdbb_char_apply(dim, direction, mode, gamma, U, X, Y, n=None, stream=None):
                                     n, _stream(stream)))
 
 
+def fdbb_roe_average(dim, gamma, UL, UR, Uh, n=None, stream=None):
+    ul, ldl = _fields(UL, dim + 2, "UL")
+    ur, ldr = _fields(UR, dim + 2, "UR")
+    uh, ldh = _fields(Uh, dim + 2, "Uh")
+    n = UL.shape[1] if n is None else n
+    check(library().fdbb_roe_average(dim, gamma, dtype_code(UL.dtype), ul, ldl, ur, ldr, uh, ldh, n,
+                                     _stream(stream)))
+
+
 def fdbb_set_launch_config(op, dim, dtype, block, ppt, grid_cap=0, nontemporal=1):
     op = OPS[op] if isinstance(op, str) else op
     check(library().fdbb_set_launch_config(op, dim, dtype, block, ppt, grid_cap, nontemporal))
@@ -444,6 +454,14 @@ def eigenvectors(U, gamma=1.4, left=True, right=True, stream=None):
     R = empty_blocks(dim, U.shape[1], U.dtype, U.device) if right else None
     fdbb_eigenvectors(dim, gamma, U, L, R, stream=stream)
     return L, R
+
+
+def roe_average(UL, UR, gamma=1.4, stream=None):
+    """Roe-averaged conservative state between UL and UR."""
+    dim = _dim_of(UL)
+    Uh = empty_fields(dim + 2, UL.shape[1], UL.dtype, UL.device)
+    fdbb_roe_average(dim, gamma, UL, UR, Uh, stream=stream)
+    return Uh
 
 
 def char_apply(U, X, direction, mode=0, gamma=1.4, stream=None):

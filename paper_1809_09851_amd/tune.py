@@ -40,11 +40,11 @@ def arch_key() -> str:
     return f"{arch}/hip{torch.version.hip}"
 
 
-def _state(dim, n, dtype):
+def _state(dim, n, dtype, seed=1234):
     """A valid conservative state built on the device (no host data needed)."""
     V = F.empty_fields(dim + 2, n, dtype)
     g = torch.Generator(device="cuda")
-    g.manual_seed(1234)
+    g.manual_seed(seed)
     V[0].uniform_(0.5, 2.0, generator=g)
     for k in range(dim):
         V[1 + k].normal_(0.0, 0.5, generator=g)
@@ -99,6 +99,10 @@ def workload(op: str, dim: int, dtype, n: int):
         X = F.empty_fields(K, n, dtype).normal_()
         Y = F.empty_fields(K, n, dtype)
         return lambda: F.fdbb_char_apply(dim, 0, 0, GAMMA, U, X, Y)
+    if op == "roe_average":
+        UR = _state(dim, n, dtype, seed=4321)
+        Uh = F.empty_fields(K, n, dtype)
+        return lambda: F.fdbb_roe_average(dim, GAMMA, U, UR, Uh)
     if op == "adjoint":
         Fb = F.empty_fields(K * dim, n, dtype).normal_()
         Ub = F.empty_fields(K, n, dtype)
@@ -112,7 +116,8 @@ def bytes_per_point(op: str, dim: int, elem: int) -> int:
     per = {"cons2prim": 2 * K, "prim2cons": 2 * K, "cons2char": 2 * K, "char2cons": 2 * K,
            "eos": K + 2, "v_mag2": dim + 2, "flux": K + K * dim, "flux_jacobian": K + dim * K * K,
            "riemann_invariants": K + 2 * dim + 1, "fused": K + K * dim + dim * K * K + 2 * dim + 1,
-           "adjoint": K * K, "eigenvectors": K + 2 * dim * K * K, "char_apply": 3 * K}[op]
+           "adjoint": K * K, "eigenvectors": K + 2 * dim * K * K, "char_apply": 3 * K,
+           "roe_average": 3 * K}[op]
     return per * elem
 
 

@@ -79,3 +79,16 @@ def blocks_error(x: np.ndarray, y: np.ndarray) -> float:
     xf = np.asarray(x, dtype=np.float64).reshape(D * n, K * K).T
     yf = np.asarray(y, dtype=np.float64).reshape(D * n, K * K).T
     return group_error(xf, yf, [list(range(K * K))])
+
+
+def roe_error(x: np.ndarray, y: np.ndarray, UL: np.ndarray, UR: np.ndarray) -> float:
+    """Roe-averaged states: groups {rho}, {m}, {E}.  The averaged velocity
+    (a v_L + b v_R) / (a + b), a = sqrt(rho_L), b = sqrt(rho_R), cancels
+    when v_L and v_R point apart, so the momentum group is measured against
+    the size of its terms, rho^ max_k (a |v_L,k| + b |v_R,k|) / (a + b)."""
+    dim = UL.shape[0] - 2
+    a, b = np.sqrt(UL[0]), np.sqrt(UR[0])
+    vL, vR = np.abs(UL[1:dim + 1] / UL[0]), np.abs(UR[1:dim + 1] / UR[0])
+    den = (a * b) * ((a * vL + b * vR) / (a + b)).max(axis=0)
+    e = group_error(x, y, [[0], [dim + 1]])
+    return max(e, group_error(x, y, [list(range(1, dim + 1))], denom=den))

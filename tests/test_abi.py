@@ -117,6 +117,21 @@ def test_eigen_and_char_apply_checks():
     assert lib.fdbb_char_apply(2, 0, 0, 1.4, 0, A0, 128, B0, 128, B0 + 8, 128, 100, None) == F.EALIAS
 
 
+def test_roe_average_checks():
+    lib = F.library()
+    assert lib.fdbb_roe_average(4, 1.4, 0, A0, 128, B0, 128, A0 + 10**7, 128, 100, None) == F.EINVAL
+    assert lib.fdbb_roe_average(2, 1.0, 0, A0, 128, B0, 128, A0 + 10**7, 128, 100, None) == F.EINVAL
+    assert lib.fdbb_roe_average(2, 1.4, 0, None, 128, B0, 128, A0 + 10**7, 128, 100, None) == F.EINVAL
+    # the output may not partly overlap either input
+    assert lib.fdbb_roe_average(2, 1.4, 0, A0, 128, B0, 128, A0 + 8, 128, 100, None) == F.EALIAS
+    assert lib.fdbb_roe_average(2, 1.4, 0, A0, 128, B0, 128, B0 + 8, 128, 100, None) == F.EALIAS
+    assert lib.fdbb_roe_average(2, 1.4, 0, A0, 128, B0, 128, B0, 64, 100, None) == F.EINVAL
+    t = F.Task()
+    t.op, t.dim, t.dtype, t.gamma, t.n = F.OPS["roe_average"], 3, 1, 1.4, 100
+    t.in0, t.ld_in0, t.in1, t.ld_in1, t.out0, t.ld_out0 = A0, 128, B0, 128, B0, 128
+    assert lib.fdbb_task_check(ctypes.byref(t)) == F.OK  # in place over UR
+
+
 def test_server_rejects_bad_arguments():
     lib = F.library()
     h = ctypes.c_void_p()
