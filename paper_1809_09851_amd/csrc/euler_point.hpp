@@ -218,11 +218,19 @@ __device__ __forceinline__ Waves make_waves(const Gas &g, const State<D> &s)
     return w;
 }
 
+// x^y for the positive bases of the entropy and of its inverse, as
+// exp(y log x): the general pow also serves negative bases, integer
+// exponents and a doubled-precision logarithm, which these uses do not need.
+// The exponent y log x carries an absolute error of a few units in the last
+// place of |y log x|, which is the relative error of the result (below
+// 1e-14 for |y log x| < 40).  x <= 0 gives NaN or the limit at 0, as pow.
+__device__ __forceinline__ double pos_pow(double x, double y) { return exp(y * log(x)); }
+
 // Entropy s = p / rho^gamma.
 template <int D>
 __device__ __forceinline__ double entropy(const Gas &g, const State<D> &s)
 {
-    return s.p * pow(s.rho, -g.gamma);
+    return s.p * pos_pow(s.rho, -g.gamma);
 }
 
 // Adjoint contribution of direction d: ubar += A_d^T fb, where fb = (a,
@@ -259,18 +267,41 @@ __device__ __forceinline__ void adjoint_accumulate(const Gas &g, const State<D> 
 // and total enthalpy H = (E + p) / rho averaged with weights a and b; the
 // pressure follows from H^ = gamma p^ / ((gamma - 1) rho^) + |v^|^2 / 2.
 // The flux Jacobians at this state satisfy A(U^)(U_R - U_L) = F(U_R) - F(U_L).
+// One side at a time is folded into weighted sums, so that only those sums
+// and one raw state are live at once.
+
+// Adds sqrt(rho) (v, H) of the conservative state u to sum[0..D] (v, then
+// H); returns sqrt(rho).  With r = 1/sqrt(rho): sqrt(rho) v = m r,
+// sqrt(rho) H = (E + p) r and rho |v|^2 = |m|^2 r^2, so one reciprocal
+// square root replaces a square root and a division.
 template <int D>
-__device__ __forceinline__ void roe_average(const Gas &g, const State<D> &l, const State<D> &r, double *out)
+__device__ __forceinline__ double roe_accumulate(const Gas &g, const double *u, double *sum)
 {
-    const double a = sqrt(l.rho), b = sqrt(r.rho);
+    const double r = rsqrt(u[0]);
+    double mm = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        mm += u[1 + k] * u[1 + k];
+        sum[k] += u[1 + k] * r;
+    }
+    const double p = g.g1 * (u[D + 1] - 0.5 * mm * (r * r));
+    sum[D] += (u[D + 1] + p) * r;
+    return u[0] * r;
+}
+
+// Completes the average from the weighted sums of both sides and the two
+// weights a = sqrt(rho_L), b = sqrt(rho_R).
+template <int D>
+__device__ __forceinline__ void roe_finish(const Gas &g, const double *sum, double a, double b, double *out)
+{
     const double w = 1.0 / (a + b);
     const double rho = a * b;
-    const double H = (a * (l.E + l.p) * l.rinv + b * (r.E + r.p) * r.rinv) * w;
+    const double H = sum[D] * w;
     double q = 0.0;
     out[0] = rho;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        const double v = (a * l.v[k] + b * r.v[k]) * w;
+        const double v = sum[k] * w;
         q += v * v;
         out[1 + k] = rho * v;
     }

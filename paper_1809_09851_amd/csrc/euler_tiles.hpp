@@ -226,6 +226,8 @@ __device__ __forceinline__ void tile_prim2cons(const Args &a, int64_t tile0)
 }
 
 // Roe-averaged state between the states in in0 (left) and in1 (right).
+// Per chunk, the left states are folded into weighted sums before the right
+// states are loaded, so that one side's raw state is live at a time.
 template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void tile_roe(const Args &a, int64_t tile0)
 {
@@ -234,29 +236,49 @@ __device__ __forceinline__ void tile_roe(const Args &a, int64_t tile0)
     constexpr int W = L_t::W, NC = L_t::NC;
     const L_t L(a, tile0);
     if (!L.any()) return;
-    double ul[NC][K][W], ur[NC][K][W];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        L.template load_fields<K>(a.in0, a.ld_in0, c, ul[c]);
-        L.template load_fields<K>(a.in1, a.ld_in1, c, ur[c]);
-    }
+        double sum[W][D + 1], wl[W], wr[W];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
+        for (int j = 0; j < W; ++j)
+#pragma unroll
+            for (int k = 0; k <= D; ++k) sum[j][k] = 0.0;
+        {
+            double u[K][W];
+            L.template load_fields<K>(a.in0, a.ld_in0, c, u);
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                double uj[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) uj[k] = u[k][j];
+                wl[j] = roe_accumulate<D>(a.gas, uj, sum[j]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        {
+            double u[K][W];
+            L.template load_fields<K>(a.in1, a.ld_in1, c, u);
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                double uj[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) uj[k] = u[k][j];
+                wr[j] = roe_accumulate<D>(a.gas, uj, sum[j]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
         double out[K][W];
 #pragma unroll
         for (int j = 0; j < W; ++j) {
-            double lj[K], rj[K], hj[K];
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                lj[k] = ul[c][k][j];
-                rj[k] = ur[c][k][j];
-            }
-            roe_average<D>(a.gas, make_state<D>(a.gas, lj), make_state<D>(a.gas, rj), hj);
+            double hj[K];
+            roe_finish<D>(a.gas, sum[j], wl[j], wr[j], hj);
 #pragma unroll
             for (int k = 0; k < K; ++k) out[k][j] = hj[k];
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) L.store(a.out0, a.ld_out0, k, c, out[k]);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -474,7 +496,7 @@ __device__ __forceinline__ void tile_char2cons(const Args &a, int64_t tile0)
             const double cs = g.quarter_g1 * (wp - wm);
             const double c2 = cs * cs;
             // rho = (c^2 / (gamma s))^(1/(gamma-1)),  p = rho c^2 / gamma
-            const double rho = pow(c2 * g.inv_gamma / s, g.inv_g1);
+            const double rho = pos_pow(c2 * g.inv_gamma / s, g.inv_g1);
             const double p = rho * c2 * g.inv_gamma;
             double vp[K];
             vp[0] = rho;
