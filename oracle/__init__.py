@@ -22,6 +22,8 @@ Sections cited below are those of the FDBB paper:
                                    "characteristic variables", linearised)
   * roe_average                 -- Roe's averaged state between two states, the
                                    linearisation point of that decomposition
+  * eos_pvt                     -- Sec. 2.2, "Equations of state": p(rho, e),
+                                   T(rho, e) and c of a runtime-selected EOS
 """
 from __future__ import annotations
 
@@ -99,6 +101,8 @@ class Oracle:
         lib.oracle_char_apply.restype = _int
         lib.oracle_roe_average.argtypes = [_int, _dbl, _dp, _i64, _dp, _i64, _dp, _i64, _i64]
         lib.oracle_roe_average.restype = _int
+        lib.oracle_eos_pvt.argtypes = [_int, _int, _dp, _dp, _i64, _dp, _dp, _dp, _i64]
+        lib.oracle_eos_pvt.restype = _int
         self.lib = lib
         self.path = path
 
@@ -225,6 +229,17 @@ class Oracle:
         _check(self.lib.oracle_roe_average(dim, gamma, _ptr(UL), n, _ptr(UR), n, _ptr(Uh), n, n))
         return Uh
 
+    def eos_pvt(self, dim, eos, params, U):
+        """(p, c, T), each of shape (n,), of EOS `eos` (0 perfect gas with
+        params (c_p, c_v); 1 stiffened gas with params (gamma, p_inf, c_v))."""
+        U = _soa(U, dim + 2)
+        n = U.shape[1]
+        prm = np.zeros(3)
+        prm[:len(params)] = params
+        p, c, T = np.empty(n), np.empty(n), np.empty(n)
+        _check(self.lib.oracle_eos_pvt(dim, eos, _ptr(prm), _ptr(U), n, _ptr(p), _ptr(c), _ptr(T), n))
+        return p, c, T
+
     def fused(self, dim, gamma, U):
         """The fused pass is, by definition, the flux, the flux Jacobians and
         the Riemann invariants of the same state."""
@@ -298,3 +313,7 @@ def char_apply(dim, direction, mode, gamma, U, X):
 
 def roe_average(dim, gamma, UL, UR):
     return default().roe_average(dim, gamma, UL, UR)
+
+
+def eos_pvt(dim, eos, params, U):
+    return default().eos_pvt(dim, eos, params, U)

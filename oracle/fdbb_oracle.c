@@ -556,3 +556,53 @@ int oracle_roe_average(int dim, double gamma, const double *UL, int64_t ldL,
     }
     return 0;
 }
+
+/* Equations of state of the form f(p, V, T) = 0 behind a runtime id (Sec.
+ * 2.2, "Equations of state": each EOS supplies p(rho, e) and T(rho, e),
+ * with e the specific internal energy).  From the conservative state,
+ * e = E/rho - |v|^2/2, then per point the pressure p, the speed of sound c
+ * and the temperature T; any output may be NULL.
+ *
+ *   eos 0, perfect gas, params = (c_p, c_v):  gamma = c_p/c_v,
+ *     p = (gamma-1) rho e,  T = e / c_v,  c^2 = gamma p / rho.
+ *   eos 1, stiffened gas, params = (gamma, p_inf, c_v):
+ *     p = (gamma-1) rho e - gamma p_inf,  T = (e - p_inf/rho) / c_v,
+ *     c^2 = gamma (p + p_inf) / rho.
+ * The speed of sound is the isentropic derivative (dp/drho)_s =
+ * (dp/drho)_e + (p/rho^2) (dp/de)_rho of each p(rho, e).  Returns -1 for an
+ * unknown id. */
+int oracle_eos_pvt(int dim, int eos, const double *params, const double *U, int64_t ldU,
+                   double *p, double *c, double *T, int64_t n)
+{
+    int64_t i;
+    int k;
+    if (!dim_ok(dim) || eos < 0 || eos > 1)
+        return -1;
+    for (i = 0; i < n; ++i) {
+        double rho = U[0 * ldU + i];
+        double q = 0.0, e, pi, ci, Ti;
+        for (k = 0; k < dim; ++k) {
+            double v = U[(1 + k) * ldU + i] / rho;
+            q = q + v * v;
+        }
+        e = U[(dim + 1) * ldU + i] / rho - 0.5 * q;
+        if (eos == 0) {
+            double gamma = params[0] / params[1];
+            pi = (gamma - 1.0) * rho * e;
+            Ti = e / params[1];
+            ci = sqrt(gamma * pi / rho);
+        } else {
+            double gamma = params[0], pinf = params[1];
+            pi = (gamma - 1.0) * rho * e - gamma * pinf;
+            Ti = (e - pinf / rho) / params[2];
+            ci = sqrt(gamma * (pi + pinf) / rho);
+        }
+        if (p)
+            p[i] = pi;
+        if (c)
+            c[i] = ci;
+        if (T)
+            T[i] = Ti;
+    }
+    return 0;
+}

@@ -571,6 +571,101 @@ def pin_roe_consistency(o):
             assert np.all(H >= lo * (1 - 1e-14)) and np.all(H <= hi * (1 + 1e-14)), "H^ outside [H_L, H_R]"
 
 
+EOS_CASES = ((0, (3.5, 2.5)), (0, (1.0, 0.6)), (1, (4.4, 0.0, 1.0)), (1, (4.4, 3.0, 0.7)),
+             (1, (1.9, 0.4, 2.5)))
+
+
+def _eos_states(dim, n, seed, eos, params):
+    """Admissible states for an EOS case: rho in [0.5, 2], v ~ N(0, 0.6^2),
+    and an internal energy that keeps p + p_inf > 0."""
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.5, 2.0, n)
+    v = rng.normal(0.0, 0.6, (dim, n))
+    pinf = params[1] if eos == 1 else 0.0
+    e = pinf / rho + rng.uniform(0.5, 3.0, n)
+    E = rho * (e + 0.5 * (v * v).sum(axis=0))
+    return np.vstack([rho[None], rho[None] * v, E[None]]), rho, e
+
+
+def _with_rho_e(U, dim, rho, e):
+    """The state with density rho and specific internal energy e, keeping
+    the velocity of U."""
+    v = U[1:dim + 1] / U[0]
+    E = rho * (e + 0.5 * (v * v).sum(axis=0))
+    return np.vstack([rho[None], rho[None] * v, E[None]])
+
+
+def pin_eos_perfect_gas_thermal(o):
+    """Perfect gas with c_p, c_v (R = c_p - c_v need not be 1): states built
+    from (rho, v, T) with e = c_v T must give back T, p = rho R T and
+    c^2 = gamma R T; the same gas through the gamma-only EOS entry gives the
+    same p and c."""
+    for cp, cv in ((3.5, 2.5), (1.0, 0.6), (5.0, 3.0)):
+        for dim in (1, 2, 3):
+            rng = np.random.default_rng(70 + dim)
+            n = 50
+            rho = rng.uniform(0.5, 2.0, n)
+            v = rng.normal(0.0, 0.6, (dim, n))
+            T = rng.uniform(0.3, 1.5, n)
+            U = np.vstack([rho[None], rho[None] * v, (rho * (cv * T + 0.5 * (v * v).sum(axis=0)))[None]])
+            p, c, Tt = o.eos_pvt(dim, 0, (cp, cv), U)
+            close(Tt, T, 1e-14, "T = e / c_v")
+            close(p, rho * (cp - cv) * T, 1e-14, "p = rho R T")
+            close(c * c, cp / cv * (cp - cv) * T, 1e-14, "c^2 = gamma R T")
+            p2, c2 = o.eos(dim, cp / cv, U)
+            close(p, p2, 1e-14, "same gas, gamma-only entry (p)")
+            close(c, c2, 1e-14, "same gas, gamma-only entry (c)")
+
+
+def pin_eos_stiffened_reduces(o):
+    """With p_inf = 0 the stiffened gas is the perfect gas with c_p = gamma c_v."""
+    for g, cv in ((1.4, 2.5), (4.4, 0.7)):
+        for dim in (1, 2, 3):
+            U = _eos_states(dim, 40, 80 + dim, 0, (g * cv, cv))[0]
+            a = o.eos_pvt(dim, 1, (g, 0.0, cv), U)
+            b = o.eos_pvt(dim, 0, (g * cv, cv), U)
+            for x, y, what in zip(a, b, "pcT"):
+                close(x, y, 1e-14, f"p_inf = 0 reduction ({what})")
+
+
+def pin_eos_sound_speed_fd(o):
+    """c^2 is the isentropic derivative (dp/drho)_e + (p/rho^2)(dp/de)_rho of
+    each EOS's own p(rho, e), taken here by central differences."""
+    for eos, prm in EOS_CASES:
+        dim = 2
+        U, rho, e = _eos_states(dim, 40, 90, eos, prm)
+        p, c, _ = o.eos_pvt(dim, eos, prm, U)
+        h = 1e-5
+        pr = (o.eos_pvt(dim, eos, prm, _with_rho_e(U, dim, rho * (1 + h), e))[0]
+              - o.eos_pvt(dim, eos, prm, _with_rho_e(U, dim, rho * (1 - h), e))[0]) / (2 * h * rho)
+        pe = (o.eos_pvt(dim, eos, prm, _with_rho_e(U, dim, rho, e * (1 + h)))[0]
+              - o.eos_pvt(dim, eos, prm, _with_rho_e(U, dim, rho, e * (1 - h)))[0]) / (2 * h * e)
+        close(c * c, pr + p / rho ** 2 * pe, 1e-7, f"isentropic c^2, eos {eos} {prm}")
+
+
+def pin_eos_thermodynamic_consistency(o):
+    """p(rho, e) and T(rho, e) of one EOS must be consistent (they come from
+    one free energy): rho^2 (dT/drho)_e = T (dp/de)_rho - p (dT/de)_rho.
+    Checked by central differences; this ties T's density dependence to
+    p's (for the stiffened gas, the p_inf terms of both)."""
+    for eos, prm in EOS_CASES:
+        dim = 1
+        U, rho, e = _eos_states(dim, 40, 95, eos, prm)
+        p, _, T = o.eos_pvt(dim, eos, prm, U)
+        h = 1e-5
+
+        def at(r, ee):
+            return o.eos_pvt(dim, eos, prm, _with_rho_e(U, dim, r, ee))
+
+        Tr = (at(rho * (1 + h), e)[2] - at(rho * (1 - h), e)[2]) / (2 * h * rho)
+        Te = (at(rho, e * (1 + h))[2] - at(rho, e * (1 - h))[2]) / (2 * h * e)
+        pe = (at(rho, e * (1 + h))[0] - at(rho, e * (1 - h))[0]) / (2 * h * e)
+        lhs = rho ** 2 * Tr
+        rhs = T * pe - p * Te
+        scale = np.abs(T * pe) + np.abs(p * Te) + 1.0
+        close(lhs / scale, rhs / scale, 1e-8, f"consistency, eos {eos} {prm}", scale=1.0)
+
+
 PINS = [
     pin_worked_state,
     pin_v_mag2,
@@ -594,4 +689,8 @@ PINS = [
     pin_roe_property,
     pin_roe_product_rule,
     pin_roe_consistency,
+    pin_eos_perfect_gas_thermal,
+    pin_eos_stiffened_reduces,
+    pin_eos_sound_speed_fd,
+    pin_eos_thermodynamic_consistency,
 ]

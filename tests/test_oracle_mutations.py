@@ -62,6 +62,17 @@ MUTATIONS += [
      "p = (gamma - 1.0) * rho * (H - 0.5 * q);"),
     ("Roe energy sign", "Uh[(dim + 1) * ldH + i] = rho * H - p;", "Uh[(dim + 1) * ldH + i] = rho * H + p;"),
 ]
+MUTATIONS += [
+    ("EOS temperature uses c_p", "Ti = e / params[1];", "Ti = e / params[0];"),
+    ("EOS perfect-gas gamma inverted", "double gamma = params[0] / params[1];", "double gamma = params[1] / params[0];"),
+    ("EOS internal energy without kinetic half", "e = U[(dim + 1) * ldU + i] / rho - 0.5 * q;",
+     "e = U[(dim + 1) * ldU + i] / rho - q;"),
+    ("stiffened pressure p_inf factor", "pi = (gamma - 1.0) * rho * e - gamma * pinf;",
+     "pi = (gamma - 1.0) * rho * e - pinf;"),
+    ("stiffened temperature without p_inf", "Ti = (e - pinf / rho) / params[2];", "Ti = e / params[2];"),
+    ("stiffened sound speed without p_inf", "ci = sqrt(gamma * (pi + pinf) / rho);", "ci = sqrt(gamma * pi / rho);"),
+    ("stiffened temperature c_v slot", "Ti = (e - pinf / rho) / params[2];", "Ti = (e - pinf / rho) / params[1];"),
+]
 MUTATIONS = [m for m in MUTATIONS if m[2] is not None]
 
 
