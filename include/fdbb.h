@@ -86,7 +86,8 @@ typedef enum {
     FDBB_OP_EIGENVECTORS = 11,
     FDBB_OP_CHAR_APPLY = 12,
     FDBB_OP_ROE_AVERAGE = 13,
-    FDBB_NUM_OPS = 14
+    FDBB_OP_EOS_PVT = 14,
+    FDBB_NUM_OPS = 15
 } fdbb_op;
 
 /* Conservative -> primitive (Sec. 2.2, "Variables", conversion figure):
@@ -193,6 +194,21 @@ int fdbb_char_apply(int dim, int dir, int mode, double gamma, int dtype, const v
 int fdbb_roe_average(int dim, double gamma, int dtype, const void *UL, int64_t ldUL, const void *UR,
                      int64_t ldUR, void *Uh, int64_t ldUh, int64_t n, void *stream);
 
+/* Equations of state of the form f(p, V, T) = 0 behind a runtime id (Sec.
+ * 2.2, "Equations of state": each supplies p(rho, e) and T(rho, e), e the
+ * specific internal energy e = E/rho - |v|^2/2).  Per point: pressure p,
+ * speed of sound c (the isentropic derivative of p) and temperature T.
+ *   eos FDBB_EOS_PERFECT_GAS, params = {c_p, c_v} (c_p > c_v > 0):
+ *     gamma = c_p/c_v, p = (gamma-1) rho e, T = e/c_v, c^2 = gamma p/rho;
+ *   eos FDBB_EOS_STIFFENED_GAS, params = {gamma, p_inf, c_v} (gamma > 1,
+ *     p_inf >= 0, c_v > 0): p = (gamma-1) rho e - gamma p_inf,
+ *     T = (e - p_inf/rho)/c_v, c^2 = gamma (p + p_inf)/rho.
+ * p, c, T are single fields of n values, any of them NULL (not all).  Not a
+ * batch task (tasks carry gamma only). */
+typedef enum { FDBB_EOS_PERFECT_GAS = 0, FDBB_EOS_STIFFENED_GAS = 1 } fdbb_eos_id;
+int fdbb_eos_pvt(int dim, int eos, const double *params, int dtype, const void *U, int64_t ldU, void *p,
+                 void *c, void *T, int64_t n, void *stream);
+
 /* ---------------------------------------------------------------- tuning
  * Launch configuration per (op, dim, dtype): `block` threads per workgroup
  * (64..1024, a multiple of 64; at most 256 for the flux Jacobian and the
@@ -240,10 +256,12 @@ typedef struct {
     int64_t ld_out2;
 } fdbb_task;
 
-/* Validate one task as its single-call entry point would (no HIP call). */
+/* Validate one task as its single-call entry point would (no HIP call).
+ * FDBB_EINVAL for FDBB_OP_EOS_PVT, whose parameters a task cannot carry. */
 int fdbb_task_check(const fdbb_task *task);
 
-/* Run one task through its single-call entry point on `stream`. */
+/* Run one task through its single-call entry point on `stream` (char_apply
+ * tasks apply L; FDBB_OP_EOS_PVT is refused as above). */
 int fdbb_task_run(const fdbb_task *task, void *stream);
 
 typedef struct fdbb_batch_plan fdbb_batch_plan;
@@ -257,7 +275,9 @@ typedef struct fdbb_batch_plan fdbb_batch_plan;
  * one another's outputs are rejected (FDBB_EALIAS).  Jacobian staging needs
  * LDS; a plan holds what its first task list needs, or, when created with
  * ntasks == 0, what any task needs (later task lists needing more than the
- * plan holds are rejected with FDBB_EINVAL). */
+ * plan holds are rejected with FDBB_EINVAL).  Every op but
+ * FDBB_OP_EIGENVECTORS, FDBB_OP_CHAR_APPLY and FDBB_OP_EOS_PVT can be a
+ * task (FDBB_EINVAL otherwise). */
 int fdbb_batch_plan_create(const fdbb_task *tasks, int ntasks, int capacity, int block,
                            int ppt, int grid, int nontemporal, fdbb_batch_plan **plan);
 

@@ -22,6 +22,8 @@ struct Gas {
     double two_inv_g1;   // 2 / (gamma - 1)
     double quarter_g1;   // (gamma - 1) / 4
     double inv_gamma;    // 1 / gamma
+    double p_inf;        // stiffening pressure of the general EOS entry (0: perfect gas)
+    double inv_cv;       // 1 / c_v of the general EOS entry (0 elsewhere)
 };
 
 // Shared sub-expressions of one conservative state, computed once and reused

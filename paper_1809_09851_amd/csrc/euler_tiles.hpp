@@ -335,6 +335,43 @@ __device__ __forceinline__ void tile_eos(const Args &a, int64_t tile0)
     }
 }
 
+// General EOS entry: pressure, speed of sound and temperature of the
+// stiffened gas p = (gamma-1) rho e - gamma p_inf, T = (e - p_inf/rho)/c_v,
+// c^2 = gamma (p + p_inf)/rho, which is the perfect gas when p_inf = 0.
+// Outputs out0 (p), out1 (c), out2 (T), each optional.
+template <int D, typename T, int P, bool NT>
+__device__ __forceinline__ void tile_eos_pvt(const Args &a, int64_t tile0)
+{
+    constexpr int K = D + 2;
+    using L_t = Lane<T, P, NT>;
+    constexpr int W = L_t::W, NC = L_t::NC;
+    const L_t L(a, tile0);
+    if (!L.any()) return;
+    double u[NC][K][W];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) L.template load_fields<K>(a.in0, a.ld_in0, c, u[c]);
+    const Gas &g = a.gas;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double p[W], cs[W], t[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            double uj[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) uj[k] = u[c][k][j];
+            const State<D> s = make_state<D>(g, uj);
+            // s.p is (gamma-1) rho e; e = E/rho - |v|^2/2
+            const double e = s.E * s.rinv - 0.5 * s.q;
+            p[j] = s.p - g.gamma * g.p_inf;
+            cs[j] = sqrt(g.gamma * (p[j] + g.p_inf) * s.rinv);
+            t[j] = (e - g.p_inf * s.rinv) * g.inv_cv;
+        }
+        if (a.out0) L.store(a.out0, 0, 0, c, p);
+        if (a.out1) L.store(a.out1, 0, 0, c, cs);
+        if (a.out2) L.store(a.out2, 0, 0, c, t);
+    }
+}
+
 // The K*D flux fields of W points.
 template <int D, typename T, int P, bool NT>
 __device__ __forceinline__ void store_flux(const Lane<T, P, NT> &L, const State<D> *s, int c, void *F,

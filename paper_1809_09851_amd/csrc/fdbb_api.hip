@@ -164,6 +164,8 @@ Gas make_gas(double gamma)
     g.two_inv_g1 = 2.0 / (gamma - 1.0);
     g.quarter_g1 = 0.25 * (gamma - 1.0);
     g.inv_gamma = 1.0 / gamma;
+    g.p_inf = 0.0;
+    g.inv_cv = 0.0;
     return g;
 }
 
@@ -241,6 +243,7 @@ int family_of(int op)
     case FDBB_OP_EIGENVECTORS: return kFamEigen;
     case FDBB_OP_CHAR_APPLY: return kFamCharApply;
     case FDBB_OP_ROE_AVERAGE: return kFamRoe;
+    case FDBB_OP_EOS_PVT: return kFamEosPvt;
     default: return -1;
     }
 }
@@ -255,7 +258,8 @@ const void *kernel_for(int op, int dim, int dtype, int ppt, bool nt)
     case kFamFlux:
     case kFamRiemann:
     case kFamVmag2:
-    case kFamRoe: return kernel_pointwise(fam, dim, dtype, ppt, nt);
+    case kFamRoe:
+    case kFamEosPvt: return kernel_pointwise(fam, dim, dtype, ppt, nt);
     case kFamCons2Char:
     case kFamChar2Cons: return kernel_char(fam, dim, dtype, ppt, nt);
     case kFamFused: return kernel_fused(dim, dtype, ppt, nt);
@@ -393,6 +397,14 @@ int build_call(Call &c, const fdbb_task &t, int mode = 0)
         if ((rc = add_fields(c, t.in1, t.ld_in1, K, 1, true, true, "X"))) return rc;
         if ((rc = add_fields(c, t.out0, t.ld_out0, K, 1, false, true, "Y"))) return rc;
         break;
+    case FDBB_OP_EOS_PVT:
+        if (!t.out0 && !t.out1 && !t.out2 && t.n > 0) return fail(FDBB_EINVAL, "p, c and T must not all be NULL");
+        a.in0 = t.in0, a.ld_in0 = t.ld_in0, a.out0 = t.out0, a.out1 = t.out1, a.out2 = t.out2;
+        if ((rc = add_fields(c, t.in0, t.ld_in0, K, 1, true, true, "U"))) return rc;
+        if ((rc = add_fields(c, t.out0, 0, 1, 1, false, false, "p"))) return rc;
+        if ((rc = add_fields(c, t.out1, 0, 1, 1, false, false, "c"))) return rc;
+        if ((rc = add_fields(c, t.out2, 0, 1, 1, false, false, "T"))) return rc;
+        break;
     case FDBB_OP_ROE_AVERAGE:
         c.inplace_ok = true;
         a.in0 = t.in0, a.ld_in0 = t.ld_in0, a.in1 = t.in1, a.ld_in1 = t.ld_in1;
@@ -443,6 +455,15 @@ int build_call(Call &c, const fdbb_task &t, int mode = 0)
     default: return fail(FDBB_EINVAL, "unknown op");
     }
     return FDBB_OK;
+}
+
+// Ops a batch plan can run: everything the persistent kernel dispatches.
+// The eigenvector blocks and characteristic products have kernels of their
+// own, and the general EOS needs parameters a task does not carry.
+bool batchable(int op)
+{
+    return op >= 0 && op < FDBB_NUM_OPS && op != FDBB_OP_EIGENVECTORS && op != FDBB_OP_CHAR_APPLY &&
+           op != FDBB_OP_EOS_PVT;
 }
 
 fdbb_task make_task(int op, int dim, int dir, double gamma, int dtype, int64_t n)
@@ -587,9 +608,41 @@ int fdbb_roe_average(int dim, double gamma, int dtype, const void *UL, int64_t l
     return run(t, stream);
 }
 
+int fdbb_eos_pvt(int dim, int eos, const double *params, int dtype, const void *U, int64_t ldU, void *p,
+                 void *c, void *T, int64_t n, void *stream)
+{
+    g_last_error.clear();
+    if (!params) return fail(FDBB_EINVAL, "params must not be NULL");
+    double gamma = 0.0, p_inf = 0.0, cv = 0.0;
+    if (eos == FDBB_EOS_PERFECT_GAS) {
+        const double cp = params[0];
+        cv = params[1];
+        if (!std::isfinite(cp) || !std::isfinite(cv) || !(cv > 0.0) || !(cp > cv))
+            return fail(FDBB_EINVAL, "perfect gas needs c_p > c_v > 0");
+        gamma = cp / cv;
+    } else if (eos == FDBB_EOS_STIFFENED_GAS) {
+        gamma = params[0];
+        p_inf = params[1];
+        cv = params[2];
+        if (!std::isfinite(p_inf) || !(p_inf >= 0.0) || !std::isfinite(cv) || !(cv > 0.0))
+            return fail(FDBB_EINVAL, "stiffened gas needs p_inf >= 0 and c_v > 0");
+    } else {
+        return fail(FDBB_EINVAL, "unknown EOS id");
+    }
+    fdbb_task t = make_task(FDBB_OP_EOS_PVT, dim, 0, gamma, dtype, n);
+    t.in0 = U, t.ld_in0 = ldU, t.out0 = p, t.out1 = c, t.out2 = T;
+    Call call;
+    int rc = build_call(call, t);
+    if (rc) return rc;
+    call.a.gas.p_inf = p_inf;
+    call.a.gas.inv_cv = 1.0 / cv;
+    return launch(call, stream);
+}
+
 int fdbb_task_check(const fdbb_task *task)
 {
     if (!task) return fail(FDBB_EINVAL, "task must not be NULL");
+    if (task->op == FDBB_OP_EOS_PVT) return fail(FDBB_EINVAL, "the general EOS needs its parameters: call fdbb_eos_pvt");
     Call c;
     int rc = build_call(c, *task);
     if (!rc) rc = check_alias(c);
@@ -599,6 +652,7 @@ int fdbb_task_check(const fdbb_task *task)
 int fdbb_task_run(const fdbb_task *task, void *stream)
 {
     if (!task) return fail(FDBB_EINVAL, "task must not be NULL");
+    if (task->op == FDBB_OP_EOS_PVT) return fail(FDBB_EINVAL, "the general EOS needs its parameters: call fdbb_eos_pvt");
     return run(*task, stream);
 }
 
@@ -709,7 +763,7 @@ int stage_tasks(fdbb_batch_plan *p, const fdbb_task *tasks, int ntasks)
     std::vector<Range> all;
     size_t need_lds = 0;
     for (int b = 0; b < ntasks; ++b) {
-        if (tasks[b].op == FDBB_OP_EIGENVECTORS || tasks[b].op == FDBB_OP_CHAR_APPLY)
+        if (!batchable(tasks[b].op))
             return fail(FDBB_EINVAL, "task " + std::to_string(b) + ": op not available in batches");
         int rc = build_call(calls[b], tasks[b]);
         if (rc) return fail(rc, "task " + std::to_string(b) + ": " + g_last_error);
@@ -813,7 +867,7 @@ int fdbb_batch_plan_create(const fdbb_task *tasks, int ntasks, int capacity, int
     if (ntasks > 0 && !tasks) return fail(FDBB_EINVAL, "tasks must not be NULL");
     // Argument checks of every task come before any HIP call.
     for (int b = 0; b < ntasks; ++b) {
-        if (tasks[b].op == FDBB_OP_EIGENVECTORS || tasks[b].op == FDBB_OP_CHAR_APPLY)
+        if (!batchable(tasks[b].op))
             return fail(FDBB_EINVAL, "task " + std::to_string(b) + ": op not available in batches");
         Call c;
         int rc = build_call(c, tasks[b]);

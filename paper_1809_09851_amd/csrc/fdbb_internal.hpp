@@ -42,6 +42,7 @@ enum Family : int {
     kFamEigen,      // eigenvector blocks (staged like the Jacobian)
     kFamCharApply,  // products with L or R of one direction
     kFamRoe,        // Roe-averaged state of two states
+    kFamEosPvt,     // p, c and T of the general EOS entry
     kNumFamilies
 };
 

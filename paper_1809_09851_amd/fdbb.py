@@ -28,7 +28,9 @@ OPS = {
     "cons2prim": 0, "prim2cons": 1, "eos": 2, "flux": 3, "flux_jacobian": 4,
     "riemann_invariants": 5, "cons2char": 6, "char2cons": 7, "fused": 8, "adjoint": 9,
     "v_mag2": 10, "eigenvectors": 11, "char_apply": 12, "roe_average": 13,
+    "eos_pvt": 14,
 }
+EOS_IDS = {"perfect_gas": 0, "stiffened_gas": 1}
 ROW_ALIGN = 64  # elements; keeps every row 16-byte aligned for both dtypes
 
 _i = ctypes.c_int
@@ -90,6 +92,7 @@ def library():
         lib.fdbb_eigenvectors.argtypes = [_i, _d, _i, _p, _i64, _p, _i64, _p, _i64, _i64, _p]
         lib.fdbb_char_apply.argtypes = [_i, _i, _i, _d, _i, _p, _i64, _p, _i64, _p, _i64, _i64, _p]
         lib.fdbb_roe_average.argtypes = [_i, _d, _i, _p, _i64, _p, _i64, _p, _i64, _i64, _p]
+        lib.fdbb_eos_pvt.argtypes = [_i, _i, _p, _i, _p, _i64, _p, _p, _p, _i64, _p]
         lib.fdbb_set_launch_config.argtypes = [_i, _i, _i, _i, _i, _i, _i]
         lib.fdbb_get_launch_config.argtypes = [_i, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i),
                                                ctypes.POINTER(_i), ctypes.POINTER(_i)]
@@ -319,6 +322,18 @@ def fdbb_roe_average(dim, gamma, UL, UR, Uh, n=None, stream=None):
                                      _stream(stream)))
 
 
+def fdbb_eos_pvt(dim, eos, params, U, p=None, c=None, T=None, n=None, stream=None):
+    """General EOS entry: eos 'perfect_gas' (params c_p, c_v) or
+    'stiffened_gas' (params gamma, p_inf, c_v)."""
+    eos = EOS_IDS[eos] if isinstance(eos, str) else eos
+    prm = (ctypes.c_double * 3)(*(list(params) + [0.0] * (3 - len(params))))
+    u, ldu = _fields(U, dim + 2, "U")
+    n = U.shape[1] if n is None else n
+    ptr = [t.data_ptr() if t is not None else None for t in (p, c, T)]
+    check(library().fdbb_eos_pvt(dim, eos, ctypes.cast(prm, _p), dtype_code(U.dtype), u, ldu, *ptr, n,
+                                 _stream(stream)))
+
+
 def fdbb_set_launch_config(op, dim, dtype, block, ppt, grid_cap=0, nontemporal=1):
     op = OPS[op] if isinstance(op, str) else op
     check(library().fdbb_set_launch_config(op, dim, dtype, block, ppt, grid_cap, nontemporal))
@@ -454,6 +469,14 @@ def eigenvectors(U, gamma=1.4, left=True, right=True, stream=None):
     R = empty_blocks(dim, U.shape[1], U.dtype, U.device) if right else None
     fdbb_eigenvectors(dim, gamma, U, L, R, stream=stream)
     return L, R
+
+
+def eos_pvt(U, eos="perfect_gas", params=(3.5, 2.5), stream=None):
+    """(p, c, T) of the conservative state U under a runtime-selected EOS."""
+    dim = _dim_of(U)
+    p, c, T = (torch.empty(U.shape[1], dtype=U.dtype, device=U.device) for _ in range(3))
+    fdbb_eos_pvt(dim, eos, params, U, p, c, T, stream=stream)
+    return p, c, T
 
 
 def roe_average(UL, UR, gamma=1.4, stream=None):

@@ -99,6 +99,9 @@ def workload(op: str, dim: int, dtype, n: int):
         X = F.empty_fields(K, n, dtype).normal_()
         Y = F.empty_fields(K, n, dtype)
         return lambda: F.fdbb_char_apply(dim, 0, 0, GAMMA, U, X, Y)
+    if op == "eos_pvt":
+        p, c, T = (torch.empty(n, dtype=dtype, device="cuda") for _ in range(3))
+        return lambda: F.fdbb_eos_pvt(dim, 1, (4.4, 0.1, 2.5), U, p, c, T)
     if op == "roe_average":
         UR = _state(dim, n, dtype, seed=4321)
         Uh = F.empty_fields(K, n, dtype)
@@ -117,7 +120,7 @@ def bytes_per_point(op: str, dim: int, elem: int) -> int:
            "eos": K + 2, "v_mag2": dim + 2, "flux": K + K * dim, "flux_jacobian": K + dim * K * K,
            "riemann_invariants": K + 2 * dim + 1, "fused": K + K * dim + dim * K * K + 2 * dim + 1,
            "adjoint": K * K, "eigenvectors": K + 2 * dim * K * K, "char_apply": 3 * K,
-           "roe_average": 3 * K}[op]
+           "roe_average": 3 * K, "eos_pvt": K + 3}[op]
     return per * elem
 
 

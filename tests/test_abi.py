@@ -132,6 +132,29 @@ def test_roe_average_checks():
     assert lib.fdbb_task_check(ctypes.byref(t)) == F.OK  # in place over UR
 
 
+def test_eos_pvt_checks():
+    lib = F.library()
+    D3 = ctypes.c_double * 3
+
+    def call(eos, prm, p=B0, c=None, T=None, dim=3, n=100):
+        return lib.fdbb_eos_pvt(dim, eos, ctypes.cast(D3(*prm), ctypes.c_void_p), 0, A0, 128, p, c, T, n, None)
+
+    assert call(0, (2.5, 3.5, 0)) == F.EINVAL  # c_p < c_v
+    assert call(0, (3.5, 0.0, 0)) == F.EINVAL
+    assert call(1, (1.0, 0.1, 1.0)) == F.EINVAL  # gamma <= 1
+    assert call(1, (4.4, -1.0, 1.0)) == F.EINVAL  # p_inf < 0
+    assert call(1, (4.4, 0.1, 0.0)) == F.EINVAL  # c_v <= 0
+    assert call(2, (4.4, 0.1, 1.0)) == F.EINVAL  # unknown id
+    assert call(1, (4.4, 0.1, 1.0), p=None) == F.EINVAL  # no output
+    assert call(1, (4.4, 0.1, 1.0), dim=4) == F.EINVAL
+    assert call(1, (4.4, 0.1, 1.0), p=A0 + 8) == F.EALIAS
+    assert lib.fdbb_eos_pvt(3, 0, None, 0, A0, 128, B0, None, None, 100, None) == F.EINVAL
+    t = F.Task()
+    t.op, t.dim, t.dtype, t.gamma, t.n = F.OPS["eos_pvt"], 3, 0, 1.4, 100
+    t.in0, t.ld_in0, t.out0 = A0, 128, B0
+    assert lib.fdbb_task_check(ctypes.byref(t)) == F.EINVAL
+
+
 def test_server_rejects_bad_arguments():
     lib = F.library()
     h = ctypes.c_void_p()

@@ -252,6 +252,37 @@ def test_roe_average_in_place_and_of_equal_states(dim, dt):
     assert group_error(host(same), ULo, state_groups(dim)) <= TOL[dt]
 
 
+EOS_CASES = (("perfect_gas", (3.5, 2.5)), ("perfect_gas", (1.0, 0.6)), ("stiffened_gas", (4.4, 0.3, 0.7)),
+             ("stiffened_gas", (1.9, 0.0, 2.5)))
+
+
+@pytest.mark.parametrize("case", range(len(EOS_CASES)))
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("dim", DIMS)
+@pytest.mark.parametrize("n", (1, 65, 5003))
+def test_eos_pvt(dim, dt, n, case):
+    eos, prm = EOS_CASES[case]
+    Uo, Ug = states(dim, n, _seed(dim, n, dt, 19 + case), dt)
+    p, c, T = F.eos_pvt(Ug, eos, prm)
+    rp, rc, rT = oracle.eos_pvt(dim, F.EOS_IDS[eos], prm, Uo)
+    for x, y, what in ((p, rp, "p"), (c, rc, "c"), (T, rT, "T")):
+        # p and T of the stiffened gas are differences (rho e against p_inf):
+        # measure them against the size of their terms
+        den = None
+        if eos == "stiffened_gas" and what != "c":
+            e_abs = np.abs(oracle.eos_pvt(dim, 0, (prm[0], 1.0), Uo)[2])  # |e| via c_v = 1
+            den = (prm[0] - 1) * Uo[0] * e_abs + prm[0] * prm[1] if what == "p" else (e_abs + prm[1] / Uo[0]) / prm[2]
+        assert group_error(host(x)[None], y[None], [[0]], denom=den) <= TOL[dt], what
+
+
+def test_eos_pvt_partial_outputs():
+    Uo, Ug = states(3, 777, 5)
+    T = torch.full((777,), 7.0, dtype=torch.float64, device="cuda")
+    F.fdbb_eos_pvt(3, "stiffened_gas", (4.4, 0.3, 0.7), Ug, None, None, T)
+    rT = oracle.eos_pvt(3, 1, (4.4, 0.3, 0.7), Uo)[2]
+    assert group_error(host(T)[None], rT[None], [[0]]) <= TOL["f64"]
+
+
 # ------------------------------------------------------------ edge cases
 
 def test_zero_points_leave_outputs_untouched():
