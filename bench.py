@@ -11,7 +11,6 @@ building blocks (FP32 storage, single-op launches, 1D ops, adjoint).
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -32,28 +31,13 @@ def fused_bytes(dim: int, es: int) -> int:
 
 
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "fused3d_f64_2p24_traffic.json")
-KERNEL_SOURCES = ["euler_point.hpp", "euler_tiles.hpp", "kernels_fused.hip"]
-
-
-def kernel_hash() -> str:
-    h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1809_09851_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
 
 
 def measured_traffic(n: int):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when the kernel source changed since the counters were taken."""
-    try:
-        with open(PROFILE_TRAFFIC) as f:
-            rec = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if rec.get("kernel_hash") != kernel_hash() or rec.get("n") != n:
-        return None
-    return rec.get("bytes_per_launch")
+    from paper_1809_09851_amd import traffic
+    return traffic.load_bytes_per_launch(PROFILE_TRAFFIC, n)
 
 
 def timed_launches(fn, steps: int, warmup: int):
@@ -129,8 +113,18 @@ def cpu_baseline(n_sample: int = 1 << 24, seed: int = 1):
             t.join()
         wall += time.perf_counter() - t0
         passes += 1
+    # one core, best of 3 over the first 2^20 points, for reference
+    n1 = min(n_sample, 1 << 20)
+    U1 = np.ascontiguousarray(U[:, :n1])
+    best = float("inf")
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.flux(3, GAMMA, U1)
+        oracle.flux_jacobian(3, GAMMA, U1)
+        oracle.riemann_invariants(3, GAMMA, U1)
+        best = min(best, time.perf_counter() - t0)
     return {"value": round(passes * n_sample / wall / 1e9, 6), "unit": "Gpoints/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "single_core_value": round(n1 / best / 1e9, 6),
             "sample": f"{passes} passes over the first {n_sample} points of the 3D N=2^24 workload "
                       f"(seed 1), fused flux+Jacobians+invariants, {threads} threads on disjoint "
                       f"2^14-point ranges, {wall:.2f} s wall"}

@@ -26,7 +26,8 @@ def test_fused_bytes_per_point():
 def test_traffic_record_is_tied_to_the_kernel_source(tmp_path, monkeypatch):
     sys.path.insert(0, ROOT)
     import bench
-    rec = {"kernel_hash": bench.kernel_hash(), "n": 1 << 24, "bytes_per_launch": 1.0}
+    from paper_1809_09851_amd import traffic
+    rec = {"kernel_hash": traffic.kernel_hash(), "n": 1 << 24, "bytes_per_launch": 1.0}
     p = tmp_path / "t.json"
     p.write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "PROFILE_TRAFFIC", str(p))
@@ -35,3 +36,20 @@ def test_traffic_record_is_tied_to_the_kernel_source(tmp_path, monkeypatch):
     rec["kernel_hash"] = "stale"
     p.write_text(json.dumps(rec))
     assert bench.measured_traffic(1 << 24) is None
+
+
+def test_traffic_record_from_counter_files(tmp_path):
+    """Counters scaled by the copy probe's: a kernel that reads 40 and writes
+    776 bytes per point over 2^20 points gives back exactly those bytes."""
+    from paper_1809_09851_amd import traffic
+    n = 1 << 20
+    rows = {"fetch": [("k_fused<3>", 40 * n / 1024 / 2), ("k_copy", (1 << 30) / 1024 / 2)] * 3,
+            "write": [("k_fused<3>", 776 * n / 1024), ("k_copy", (1 << 30) / 1024)] * 3}
+    paths = {}
+    for kind, rs in rows.items():
+        p = tmp_path / f"{kind}.csv"
+        p.write_text("Kernel_Name,Counter_Value\n" + "".join(f"{k},{v}\n" for k, v in rs))
+        paths[kind] = str(p)
+    rec = traffic.build_record("k_fused", paths["fetch"], paths["write"], n)
+    assert abs(rec["fetch_scale"] - 2.0) < 1e-12 and abs(rec["write_scale"] - 1.0) < 1e-12
+    assert abs(rec["bytes_per_launch"] - 816 * n) < 1e-6 * 816 * n
