@@ -24,6 +24,7 @@ Sections cited below are those of the FDBB paper:
                                    linearisation point of that decomposition
   * eos_pvt                     -- Sec. 2.2, "Equations of state": p(rho, e),
                                    T(rho, e) and c of a runtime-selected EOS
+  * viscous_flux                -- Fig. 1, "viscous fluxes" (Navier-Stokes form)
 """
 from __future__ import annotations
 
@@ -103,6 +104,8 @@ class Oracle:
         lib.oracle_roe_average.restype = _int
         lib.oracle_eos_pvt.argtypes = [_int, _int, _dp, _dp, _i64, _dp, _dp, _dp, _i64]
         lib.oracle_eos_pvt.restype = _int
+        lib.oracle_viscous_flux.argtypes = [_int, _dbl, _dbl, _dp, _i64, _dp, _i64, _dp, _i64, _dp, _i64, _i64]
+        lib.oracle_viscous_flux.restype = _int
         self.lib = lib
         self.path = path
 
@@ -240,6 +243,19 @@ class Oracle:
         _check(self.lib.oracle_eos_pvt(dim, eos, _ptr(prm), _ptr(U), n, _ptr(p), _ptr(c), _ptr(T), n))
         return p, c, T
 
+    def viscous_flux(self, dim, mu, kappa, U, G, gT):
+        """F^v with shape (K*D, n) from U (K, n), the velocity gradient G
+        (D*D, n; field i*D + j = dv_i/dx_j) and gT (D, n)."""
+        U = _soa(U, dim + 2)
+        G = _soa(G, dim * dim)
+        gT = _soa(gT, dim)
+        n = U.shape[1]
+        if G.shape[1] != n or gT.shape[1] != n:
+            raise ValueError("inputs differ in length")
+        Fv = np.empty(((dim + 2) * dim, n))
+        _check(self.lib.oracle_viscous_flux(dim, mu, kappa, _ptr(U), n, _ptr(G), n, _ptr(gT), n, _ptr(Fv), n, n))
+        return Fv
+
     def fused(self, dim, gamma, U):
         """The fused pass is, by definition, the flux, the flux Jacobians and
         the Riemann invariants of the same state."""
@@ -317,3 +333,7 @@ def roe_average(dim, gamma, UL, UR):
 
 def eos_pvt(dim, eos, params, U):
     return default().eos_pvt(dim, eos, params, U)
+
+
+def viscous_flux(dim, mu, kappa, U, G, gT):
+    return default().viscous_flux(dim, mu, kappa, U, G, gT)

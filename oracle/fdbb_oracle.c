@@ -606,3 +606,49 @@ int oracle_eos_pvt(int dim, int eos, const double *params, const double *U, int6
     }
     return 0;
 }
+
+/* Viscous flux tensor (Fig. 1, "viscous fluxes"; the paper names it without
+ * a definition, so this is the compressible Navier-Stokes one): Newtonian
+ * stress with Stokes' hypothesis and Fourier heat conduction, constant
+ * dynamic viscosity mu and conductivity kappa.
+ *   tau_ij = mu (dv_i/dx_j + dv_j/dx_i) - (2/3) mu delta_ij div v,
+ *   F^v_d  = (0, tau_1d, ..., tau_Dd, sum_j v_j tau_jd + kappa dT/dx_d).
+ * Inputs per point: the conservative state U (v = m / rho), the velocity
+ * gradient G with field i*D + j holding dv_i/dx_j, and the temperature
+ * gradient gT (D fields).  Output in the flux tensor's layout (field
+ * r*D + d). */
+int oracle_viscous_flux(int dim, double mu, double kappa, const double *U, int64_t ldU,
+                        const double *G, int64_t ldG, const double *gT, int64_t ldT,
+                        double *Fv, int64_t ldF, int64_t n)
+{
+    int64_t i;
+    int a, b, d;
+    double tau[3][3], v[3];
+    if (!dim_ok(dim))
+        return -1;
+    for (i = 0; i < n; ++i) {
+        double rho = U[0 * ldU + i];
+        double div = 0.0;
+        for (a = 0; a < dim; ++a) {
+            v[a] = U[(1 + a) * ldU + i] / rho;
+            div = div + G[(a * dim + a) * ldG + i];
+        }
+        for (a = 0; a < dim; ++a)
+            for (b = 0; b < dim; ++b) {
+                double t = mu * (G[(a * dim + b) * ldG + i] + G[(b * dim + a) * ldG + i]);
+                if (a == b)
+                    t = t - 2.0 / 3.0 * mu * div;
+                tau[a][b] = t;
+            }
+        for (d = 0; d < dim; ++d) {
+            double work = 0.0;
+            Fv[(0 * dim + d) * ldF + i] = 0.0;
+            for (a = 0; a < dim; ++a) {
+                Fv[((1 + a) * dim + d) * ldF + i] = tau[a][d];
+                work = work + v[a] * tau[a][d];
+            }
+            Fv[((dim + 1) * dim + d) * ldF + i] = work + kappa * gT[d * ldT + i];
+        }
+    }
+    return 0;
+}

@@ -666,6 +666,97 @@ def pin_eos_thermodynamic_consistency(o):
         close(lhs / scale, rhs / scale, 1e-8, f"consistency, eos {eos} {prm}", scale=1.0)
 
 
+def _visc_inputs(dim, n, seed):
+    rng = np.random.default_rng(seed)
+    U = thermal_state(dim, n, seed, 1.4)[0]
+    return U, rng.normal(size=(dim * dim, n)), rng.normal(size=(dim, n))
+
+
+def _visc_columns(Fv, dim, i):
+    """(K, D) matrix of point i: column d is F^v_d."""
+    return flux_columns(Fv, dim, i)
+
+
+def pin_viscous_couette(o):
+    """Plane Couette flow (textbook): velocity (u, 0, 0) with the only
+    gradient dv_x/dy = s gives tau_xy = tau_yx = mu s, no normal stresses,
+    and the energy flux u mu s across y; heat flux kappa dT/dx_d adds to the
+    energy row."""
+    mu, kappa = 0.7, 0.3
+    for dim in (2, 3):
+        rng = np.random.default_rng(dim)
+        n = 8
+        rho = rng.uniform(0.5, 2.0, n)
+        u = rng.normal(size=n)
+        s = rng.normal(size=n)
+        U = np.zeros((dim + 2, n))
+        U[0], U[1], U[-1] = rho, rho * u, 3.0
+        G = np.zeros((dim * dim, n))
+        G[0 * dim + 1] = s
+        gT = rng.normal(size=(dim, n))
+        Fv = o.viscous_flux(dim, mu, kappa, U, G, gT)
+        for i in range(n):
+            M = _visc_columns(Fv, dim, i)
+            want = np.zeros((dim + 2, dim))
+            want[1, 1] = want[2, 0] = mu * s[i]
+            want[dim + 1, :] = kappa * gT[:, i]
+            want[dim + 1, 1] += u[i] * mu * s[i]
+            close(M, want, 1e-14, f"Couette {dim}D", scale=1.0)
+
+
+def pin_viscous_rigid_rotation(o):
+    """A rigid rotation (antisymmetric velocity gradient) does no viscous
+    work and carries no stress: only the heat flux remains."""
+    for dim in (2, 3):
+        U, G, gT = _visc_inputs(dim, 20, 110 + dim)
+        Gm = G.reshape(dim, dim, -1)
+        G = (Gm - Gm.transpose(1, 0, 2)).reshape(dim * dim, -1)
+        Fv = o.viscous_flux(dim, 0.9, 0.4, U, G, gT)
+        want = np.zeros_like(Fv)
+        for d in range(dim):
+            want[(dim + 1) * dim + d] = 0.4 * gT[d]
+        close(Fv, want, 1e-14, f"rigid rotation {dim}D", scale=1.0)
+
+
+def pin_viscous_stokes(o):
+    """Stokes' hypothesis: in 3D the stress is trace-free, so a pure
+    expansion (gradient a I) carries no stress; the stress is symmetric for
+    any gradient; F^v is linear in (mu, kappa)."""
+    U, G, gT = _visc_inputs(3, 30, 120)
+    Fv = o.viscous_flux(3, 0.8, 0.5, U, G, gT)
+    for i in range(30):
+        tau = _visc_columns(Fv, 3, i)[1:4]
+        close(tau, tau.T, 1e-15, "stress symmetry", scale=np.abs(tau).max())
+        close(np.trace(tau), 0.0, 1e-14, "trace-free stress", scale=np.abs(tau).max())
+    a = np.random.default_rng(5).normal(size=30)
+    Gi = np.zeros((9, 30))
+    for k in range(3):
+        Gi[k * 3 + k] = a
+    Fi = o.viscous_flux(3, 0.8, 0.5, U, Gi, np.zeros((3, 30)))
+    close(Fi, np.zeros_like(Fi), 1e-14, "pure expansion", scale=np.abs(a).max())
+    close(o.viscous_flux(3, 1.6, 1.0, U, G, gT), 2.0 * Fv, 1e-15, "linear in (mu, kappa)")
+
+
+def pin_viscous_rotation(o):
+    """Frame rotation Q: with v' = Q v, G' = Q G Q^T, grad T' = Q grad T,
+    the stress turns as tau' = Q tau Q^T and the energy flux as Q q."""
+    rng = np.random.default_rng(130)
+    for dim in (2, 3):
+        U, G, gT = _visc_inputs(dim, 12, 131 + dim)
+        Fv = o.viscous_flux(dim, 0.6, 0.2, U, G, gT)
+        for i in range(12):
+            Q = _rotation(dim, rng)
+            v = U[1:dim + 1, i] / U[0, i]
+            Up = U[:, i:i + 1].copy()
+            Up[1:dim + 1, 0] = U[0, i] * (Q @ v)
+            Gp = (Q @ G[:, i].reshape(dim, dim) @ Q.T).reshape(dim * dim, 1)
+            gp = (Q @ gT[:, i]).reshape(dim, 1)
+            Mp = _visc_columns(o.viscous_flux(dim, 0.6, 0.2, Up, Gp, gp), dim, 0)
+            M = _visc_columns(Fv, dim, i)
+            close(Mp[1:dim + 1], Q @ M[1:dim + 1] @ Q.T, 1e-13, f"stress rotation {dim}D")
+            close(Mp[dim + 1], Q @ M[dim + 1], 1e-13, f"energy flux rotation {dim}D")
+
+
 PINS = [
     pin_worked_state,
     pin_v_mag2,
@@ -693,4 +784,8 @@ PINS = [
     pin_eos_stiffened_reduces,
     pin_eos_sound_speed_fd,
     pin_eos_thermodynamic_consistency,
+    pin_viscous_couette,
+    pin_viscous_rigid_rotation,
+    pin_viscous_stokes,
+    pin_viscous_rotation,
 ]

@@ -73,6 +73,18 @@ MUTATIONS += [
     ("stiffened sound speed without p_inf", "ci = sqrt(gamma * (pi + pinf) / rho);", "ci = sqrt(gamma * pi / rho);"),
     ("stiffened temperature c_v slot", "Ti = (e - pinf / rho) / params[2];", "Ti = (e - pinf / rho) / params[1];"),
 ]
+MUTATIONS += [
+    ("viscous bulk factor", "t = t - 2.0 / 3.0 * mu * div;", "t = t - 1.0 / 3.0 * mu * div;"),
+    ("viscous stress not symmetrised", "double t = mu * (G[(a * dim + b) * ldG + i] + G[(b * dim + a) * ldG + i]);",
+     "double t = 2.0 * mu * G[(a * dim + b) * ldG + i];"),
+    ("viscous heat flux dropped", "Fv[((dim + 1) * dim + d) * ldF + i] = work + kappa * gT[d * ldT + i];",
+     "Fv[((dim + 1) * dim + d) * ldF + i] = work;"),
+    ("viscous layout transposed", "Fv[((1 + a) * dim + d) * ldF + i] = tau[a][d];",
+     "Fv[(d * (dim + 2) + 1 + a) * ldF + i] = tau[a][d];"),
+    ("viscous work uses the flux direction velocity", "work = work + v[a] * tau[a][d];",
+     "work = work + v[d] * tau[a][d];"),
+    ("viscous velocity not divided", "v[a] = U[(1 + a) * ldU + i] / rho;", "v[a] = U[(1 + a) * ldU + i];"),
+]
 MUTATIONS = [m for m in MUTATIONS if m[2] is not None]
 
 
