@@ -379,7 +379,8 @@ def bench_ops(steps: int, warmup: int, dims=(3,), dtypes=("f64", "f32")):
     from paper_1809_09851_amd import tune
     out = {}
     ops = ("cons2prim", "prim2cons", "eos", "v_mag2", "flux", "flux_jacobian", "riemann_invariants",
-           "cons2char", "char2cons", "adjoint", "eigenvectors", "char_apply", "roe_average", "eos_pvt")
+           "cons2char", "char2cons", "adjoint", "eigenvectors", "char_apply", "roe_average", "eos_pvt",
+           "viscous_flux")
     for dim in dims:
         for dt in dtypes:
             dtype = torch.float64 if dt == "f64" else torch.float32

@@ -87,7 +87,8 @@ typedef enum {
     FDBB_OP_CHAR_APPLY = 12,
     FDBB_OP_ROE_AVERAGE = 13,
     FDBB_OP_EOS_PVT = 14,
-    FDBB_NUM_OPS = 15
+    FDBB_OP_VISCOUS_FLUX = 15,
+    FDBB_NUM_OPS = 16
 } fdbb_op;
 
 /* Conservative -> primitive (Sec. 2.2, "Variables", conversion figure):
@@ -209,6 +210,20 @@ typedef enum { FDBB_EOS_PERFECT_GAS = 0, FDBB_EOS_STIFFENED_GAS = 1 } fdbb_eos_i
 int fdbb_eos_pvt(int dim, int eos, const double *params, int dtype, const void *U, int64_t ldU, void *p,
                  void *c, void *T, int64_t n, void *stream);
 
+/* Viscous flux tensor (Fig. 1, "viscous fluxes", named there without a
+ * definition; this is the compressible Navier-Stokes one): Newtonian stress
+ * with Stokes' hypothesis and Fourier heat conduction, constant dynamic
+ * viscosity mu >= 0 and conductivity kappa >= 0:
+ *   tau_ij = mu (dv_i/dx_j + dv_j/dx_i) - (2/3) mu delta_ij div v,
+ *   F^v_d  = (0, tau_1d .. tau_Dd, sum_j v_j tau_jd + kappa dT/dx_d).
+ * Inputs: U (K fields; v = m/rho), the velocity gradient G (D*D fields,
+ * field i*D + j = dv_i/dx_j) and the temperature gradient gradT (D fields).
+ * Fv has the flux tensor's K*D fields (field r*D + d; the mass row is
+ * written as zeros).  Not a batch task. */
+int fdbb_viscous_flux(int dim, double mu, double kappa, int dtype, const void *U, int64_t ldU, const void *G,
+                      int64_t ldG, const void *gradT, int64_t ldGT, void *Fv, int64_t ldFv, int64_t n,
+                      void *stream);
+
 /* ---------------------------------------------------------------- tuning
  * Launch configuration per (op, dim, dtype): `block` threads per workgroup
  * (64..1024, a multiple of 64; at most 256 for the flux Jacobian and the
@@ -257,11 +272,13 @@ typedef struct {
 } fdbb_task;
 
 /* Validate one task as its single-call entry point would (no HIP call).
- * FDBB_EINVAL for FDBB_OP_EOS_PVT, whose parameters a task cannot carry. */
+ * FDBB_EINVAL for FDBB_OP_EOS_PVT and FDBB_OP_VISCOUS_FLUX, whose
+ * parameters and inputs a task cannot carry. */
 int fdbb_task_check(const fdbb_task *task);
 
 /* Run one task through its single-call entry point on `stream` (char_apply
- * tasks apply L; FDBB_OP_EOS_PVT is refused as above). */
+ * tasks apply L; FDBB_OP_EOS_PVT and FDBB_OP_VISCOUS_FLUX are refused as
+ * above). */
 int fdbb_task_run(const fdbb_task *task, void *stream);
 
 typedef struct fdbb_batch_plan fdbb_batch_plan;
@@ -276,8 +293,8 @@ typedef struct fdbb_batch_plan fdbb_batch_plan;
  * LDS; a plan holds what its first task list needs, or, when created with
  * ntasks == 0, what any task needs (later task lists needing more than the
  * plan holds are rejected with FDBB_EINVAL).  Every op but
- * FDBB_OP_EIGENVECTORS, FDBB_OP_CHAR_APPLY and FDBB_OP_EOS_PVT can be a
- * task (FDBB_EINVAL otherwise). */
+ * FDBB_OP_EIGENVECTORS, FDBB_OP_CHAR_APPLY, FDBB_OP_EOS_PVT and
+ * FDBB_OP_VISCOUS_FLUX can be a task (FDBB_EINVAL otherwise). */
 int fdbb_batch_plan_create(const fdbb_task *tasks, int ntasks, int capacity, int block,
                            int ppt, int grid, int nontemporal, fdbb_batch_plan **plan);
 

@@ -24,6 +24,8 @@ struct Gas {
     double inv_gamma;    // 1 / gamma
     double p_inf;        // stiffening pressure of the general EOS entry (0: perfect gas)
     double inv_cv;       // 1 / c_v of the general EOS entry (0 elsewhere)
+    double mu;           // dynamic viscosity of the viscous flux (0 elsewhere)
+    double kappa;        // heat conductivity of the viscous flux (0 elsewhere)
 };
 
 // Shared sub-expressions of one conservative state, computed once and reused

@@ -25,6 +25,8 @@ struct Args {
     int64_t ld_in0;
     const void *in1;
     int64_t ld_in1;
+    const void *in2;
+    int64_t ld_in2;
     void *out0;
     int64_t ld_out0;
     void *out1;
@@ -369,6 +371,65 @@ __device__ __forceinline__ void tile_eos_pvt(const Args &a, int64_t tile0)
         if (a.out0) L.store(a.out0, 0, 0, c, p);
         if (a.out1) L.store(a.out1, 0, 0, c, cs);
         if (a.out2) L.store(a.out2, 0, 0, c, t);
+    }
+}
+
+// Viscous flux tensor from the state (in0, K fields), the velocity gradient
+// (in1, D*D fields, field i*D + j = dv_i/dx_j) and the temperature gradient
+// (in2, D fields), in the flux tensor's layout (out0, field r*D + d):
+// F^v_d = (0, tau_1d .. tau_Dd, sum_j v_j tau_jd + kappa dT/dx_d) with
+// tau_ij = mu (dv_i/dx_j + dv_j/dx_i) - (2/3) mu delta_ij div v.  Loads go
+// chunk by chunk (K + D*D + D input fields per point) and each stress
+// entry is stored as soon as it is formed.
+template <int D, typename T, int P, bool NT>
+__device__ __forceinline__ void tile_viscous(const Args &a, int64_t tile0)
+{
+    constexpr int K = D + 2;
+    using L_t = Lane<T, P, NT>;
+    constexpr int W = L_t::W, NC = L_t::NC;
+    const L_t L(a, tile0);
+    if (!L.any()) return;
+    const double mu = a.gas.mu, kappa = a.gas.kappa;
+    const double zero[W] = {};
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double gv[D * D][W], v[D][W], bulk[W];
+        {
+            double u[K][W];
+            L.template load_fields<K>(a.in0, a.ld_in0, c, u);
+            L.template load_fields<D * D>(a.in1, a.ld_in1, c, gv);
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                const double rinv = 1.0 / u[0][j];
+                double div = 0.0;
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    v[i][j] = u[1 + i][j] * rinv;
+                    div += gv[i * D + i][j];
+                }
+                bulk[j] = (2.0 / 3.0) * mu * div;
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            L.store(a.out0, a.ld_out0, d, c, zero);
+            double e[W];
+            L.load(a.in2, a.ld_in2, d, c, e);
+#pragma unroll
+            for (int j = 0; j < W; ++j) e[j] *= kappa;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                double t[W];
+#pragma unroll
+                for (int j = 0; j < W; ++j) {
+                    t[j] = mu * (gv[i * D + d][j] + gv[d * D + i][j]) - (i == d ? bulk[j] : 0.0);
+                    e[j] += v[i][j] * t[j];
+                }
+                L.store(a.out0, a.ld_out0, (1 + i) * D + d, c, t);
+            }
+            L.store(a.out0, a.ld_out0, (D + 1) * D + d, c, e);
+        }
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 

@@ -97,9 +97,11 @@ void init_configs()
         for (int d = 0; d < 3; ++d)
             for (int t = 0; t < 2; ++t) {
                 Config c;
-                const bool jac = (op == FDBB_OP_FLUX_JACOBIAN || op == FDBB_OP_FUSED);
+                // one point per thread where a point's registers are many
+                // (staged Jacobian blocks; the viscous flux's 2D + K*D fields)
+                const bool wide = (op == FDBB_OP_FLUX_JACOBIAN || op == FDBB_OP_FUSED || op == FDBB_OP_VISCOUS_FLUX);
                 c.block = 256;
-                c.ppt = jac ? 1 : (t == FDBB_F64 ? 2 : 4);
+                c.ppt = wide ? 1 : (t == FDBB_F64 ? 2 : 4);
                 c.grid_cap = 0;
                 c.nt = 1;
                 g_cfg[op][d][t].store(pack(c));
@@ -166,6 +168,8 @@ Gas make_gas(double gamma)
     g.inv_gamma = 1.0 / gamma;
     g.p_inf = 0.0;
     g.inv_cv = 0.0;
+    g.mu = 0.0;
+    g.kappa = 0.0;
     return g;
 }
 
@@ -215,13 +219,13 @@ int check_alias(const Call &c)
 bool vector_ok(const Call &c)
 {
     const size_t es = elem_size(c.dtype);
-    const void *bases[5] = {c.a.in0, c.a.in1, c.a.out0, c.a.out1, c.a.out2};
-    const int64_t lds[5] = {c.a.ld_in0, c.a.ld_in1, c.a.ld_out0, c.a.ld_out1, c.a.ld_out2};
-    for (int k = 0; k < 5; ++k) {
+    const void *bases[6] = {c.a.in0, c.a.in1, c.a.in2, c.a.out0, c.a.out1, c.a.out2};
+    const int64_t lds[6] = {c.a.ld_in0, c.a.ld_in1, c.a.ld_in2, c.a.ld_out0, c.a.ld_out1, c.a.ld_out2};
+    const size_t units[6] = {1, 1, 1, c.unit_out0, c.unit_out1, 1};
+    for (int k = 0; k < 6; ++k) {
         if (!bases[k]) continue;
         if ((uintptr_t)bases[k] % 16 != 0) return false;
-        const size_t unit = (k == 3) ? c.unit_out1 : (k == 2 ? c.unit_out0 : 1);
-        if (((size_t)lds[k] * unit * es) % 16 != 0) return false;
+        if (((size_t)lds[k] * units[k] * es) % 16 != 0) return false;
     }
     return true;
 }
@@ -244,6 +248,7 @@ int family_of(int op)
     case FDBB_OP_CHAR_APPLY: return kFamCharApply;
     case FDBB_OP_ROE_AVERAGE: return kFamRoe;
     case FDBB_OP_EOS_PVT: return kFamEosPvt;
+    case FDBB_OP_VISCOUS_FLUX: return kFamViscous;
     default: return -1;
     }
 }
@@ -259,7 +264,8 @@ const void *kernel_for(int op, int dim, int dtype, int ppt, bool nt)
     case kFamRiemann:
     case kFamVmag2:
     case kFamRoe:
-    case kFamEosPvt: return kernel_pointwise(fam, dim, dtype, ppt, nt);
+    case kFamEosPvt:
+    case kFamViscous: return kernel_pointwise(fam, dim, dtype, ppt, nt);
     case kFamCons2Char:
     case kFamChar2Cons: return kernel_char(fam, dim, dtype, ppt, nt);
     case kFamFused: return kernel_fused(dim, dtype, ppt, nt);
@@ -452,6 +458,8 @@ int build_call(Call &c, const fdbb_task &t, int mode = 0)
             return rc;
         if ((rc = add_fields(c, t.out0, t.ld_out0, K, 1, false, true, "Ubar"))) return rc;
         break;
+    case FDBB_OP_VISCOUS_FLUX:
+        return fail(FDBB_EINVAL, "the viscous flux needs its gradients and coefficients: call fdbb_viscous_flux");
     default: return fail(FDBB_EINVAL, "unknown op");
     }
     return FDBB_OK;
@@ -463,7 +471,7 @@ int build_call(Call &c, const fdbb_task &t, int mode = 0)
 bool batchable(int op)
 {
     return op >= 0 && op < FDBB_NUM_OPS && op != FDBB_OP_EIGENVECTORS && op != FDBB_OP_CHAR_APPLY &&
-           op != FDBB_OP_EOS_PVT;
+           op != FDBB_OP_EOS_PVT && op != FDBB_OP_VISCOUS_FLUX;
 }
 
 fdbb_task make_task(int op, int dim, int dir, double gamma, int dtype, int64_t n)
@@ -637,6 +645,29 @@ int fdbb_eos_pvt(int dim, int eos, const double *params, int dtype, const void *
     call.a.gas.p_inf = p_inf;
     call.a.gas.inv_cv = 1.0 / cv;
     return launch(call, stream);
+}
+
+int fdbb_viscous_flux(int dim, double mu, double kappa, int dtype, const void *U, int64_t ldU, const void *G,
+                      int64_t ldG, const void *gradT, int64_t ldGT, void *Fv, int64_t ldFv, int64_t n,
+                      void *stream)
+{
+    Call c;
+    // gamma does not enter the viscous flux; any valid value passes the checks
+    int rc = begin(c, FDBB_OP_VISCOUS_FLUX, dim, 2.0, dtype, n);
+    if (rc) return rc;
+    if (!std::isfinite(mu) || !(mu >= 0.0) || !std::isfinite(kappa) || !(kappa >= 0.0))
+        return fail(FDBB_EINVAL, "mu and kappa must be finite and >= 0");
+    const int64_t D = dim, K = D + 2;
+    Args &a = c.a;
+    a.in0 = U, a.ld_in0 = ldU, a.in1 = G, a.ld_in1 = ldG, a.in2 = gradT, a.ld_in2 = ldGT;
+    a.out0 = Fv, a.ld_out0 = ldFv;
+    a.gas.mu = mu;
+    a.gas.kappa = kappa;
+    if ((rc = add_fields(c, U, ldU, K, 1, true, true, "U"))) return rc;
+    if ((rc = add_fields(c, G, ldG, D * D, 1, true, true, "G"))) return rc;
+    if ((rc = add_fields(c, gradT, ldGT, D, 1, true, true, "gradT"))) return rc;
+    if ((rc = add_fields(c, Fv, ldFv, K * D, 1, false, true, "Fv"))) return rc;
+    return launch(c, stream);
 }
 
 int fdbb_task_check(const fdbb_task *task)

@@ -43,6 +43,7 @@ enum Family : int {
     kFamCharApply,  // products with L or R of one direction
     kFamRoe,        // Roe-averaged state of two states
     kFamEosPvt,     // p, c and T of the general EOS entry
+    kFamViscous,    // viscous flux tensor
     kNumFamilies
 };
 

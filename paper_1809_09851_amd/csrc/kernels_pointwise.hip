@@ -1,6 +1,7 @@
 // Single-operation kernels for the pointwise building blocks: cons2prim,
 // prim2cons, EOS (perfect gas, and the general entry with temperature),
-// flux tensor, Riemann invariants, |v|^2 and the Roe-averaged state.  Each workgroup loops
+// inviscid and viscous flux tensors, Riemann invariants, |v|^2 and the
+// Roe-averaged state.  Each workgroup loops
 // over tiles of blockDim.x * P points (grid-stride when the grid is capped).
 #include "fdbb_internal.hpp"
 
@@ -20,6 +21,7 @@ __global__ __launch_bounds__(1024) void k_pointwise(Args a, int64_t ntiles)
         else if constexpr (FAM == kFamVmag2) tile_vmag2<D, T, P, NT>(a, tile0);
         else if constexpr (FAM == kFamRoe) tile_roe<D, T, P, NT>(a, tile0);
         else if constexpr (FAM == kFamEosPvt) tile_eos_pvt<D, T, P, NT>(a, tile0);
+        else if constexpr (FAM == kFamViscous) tile_viscous<D, T, P, NT>(a, tile0);
     }
 }
 
@@ -66,6 +68,7 @@ const void *kernel_pointwise(int family, int dim, int dtype, int ppt, bool nt)
     case kFamVmag2: return pick<kFamVmag2>(dim, dtype, ppt, nt);
     case kFamRoe: return pick<kFamRoe>(dim, dtype, ppt, nt);
     case kFamEosPvt: return pick<kFamEosPvt>(dim, dtype, ppt, nt);
+    case kFamViscous: return pick<kFamViscous>(dim, dtype, ppt, nt);
     default: return nullptr;
     }
 }

@@ -28,7 +28,7 @@ OPS = {
     "cons2prim": 0, "prim2cons": 1, "eos": 2, "flux": 3, "flux_jacobian": 4,
     "riemann_invariants": 5, "cons2char": 6, "char2cons": 7, "fused": 8, "adjoint": 9,
     "v_mag2": 10, "eigenvectors": 11, "char_apply": 12, "roe_average": 13,
-    "eos_pvt": 14,
+    "eos_pvt": 14, "viscous_flux": 15,
 }
 EOS_IDS = {"perfect_gas": 0, "stiffened_gas": 1}
 ROW_ALIGN = 64  # elements; keeps every row 16-byte aligned for both dtypes
@@ -93,6 +93,7 @@ def library():
         lib.fdbb_char_apply.argtypes = [_i, _i, _i, _d, _i, _p, _i64, _p, _i64, _p, _i64, _i64, _p]
         lib.fdbb_roe_average.argtypes = [_i, _d, _i, _p, _i64, _p, _i64, _p, _i64, _i64, _p]
         lib.fdbb_eos_pvt.argtypes = [_i, _i, _p, _i, _p, _i64, _p, _p, _p, _i64, _p]
+        lib.fdbb_viscous_flux.argtypes = [_i, _d, _d, _i, _p, _i64, _p, _i64, _p, _i64, _p, _i64, _i64, _p]
         lib.fdbb_set_launch_config.argtypes = [_i, _i, _i, _i, _i, _i, _i]
         lib.fdbb_get_launch_config.argtypes = [_i, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i),
                                                ctypes.POINTER(_i), ctypes.POINTER(_i)]
@@ -334,6 +335,16 @@ def fdbb_eos_pvt(dim, eos, params, U, p=None, c=None, T=None, n=None, stream=Non
                                  _stream(stream)))
 
 
+def fdbb_viscous_flux(dim, mu, kappa, U, G, gradT, Fv, n=None, stream=None):
+    u, ldu = _fields(U, dim + 2, "U")
+    g, ldg = _fields(G, dim * dim, "G")
+    t, ldt = _fields(gradT, dim, "gradT")
+    f, ldf = _fields(Fv, (dim + 2) * dim, "Fv")
+    n = U.shape[1] if n is None else n
+    check(library().fdbb_viscous_flux(dim, mu, kappa, dtype_code(U.dtype), u, ldu, g, ldg, t, ldt, f, ldf, n,
+                                      _stream(stream)))
+
+
 def fdbb_set_launch_config(op, dim, dtype, block, ppt, grid_cap=0, nontemporal=1):
     op = OPS[op] if isinstance(op, str) else op
     check(library().fdbb_set_launch_config(op, dim, dtype, block, ppt, grid_cap, nontemporal))
@@ -469,6 +480,15 @@ def eigenvectors(U, gamma=1.4, left=True, right=True, stream=None):
     R = empty_blocks(dim, U.shape[1], U.dtype, U.device) if right else None
     fdbb_eigenvectors(dim, gamma, U, L, R, stream=stream)
     return L, R
+
+
+def viscous_flux(U, G, gradT, mu, kappa, stream=None):
+    """Viscous flux tensor (K*D fields, flux tensor layout) of the state U
+    with velocity gradient G (D*D fields) and temperature gradient gradT."""
+    dim = _dim_of(U)
+    Fv = empty_fields((dim + 2) * dim, U.shape[1], U.dtype, U.device)
+    fdbb_viscous_flux(dim, mu, kappa, U, G, gradT, Fv, stream=stream)
+    return Fv
 
 
 def eos_pvt(U, eos="perfect_gas", params=(3.5, 2.5), stream=None):

@@ -99,6 +99,11 @@ def workload(op: str, dim: int, dtype, n: int):
         X = F.empty_fields(K, n, dtype).normal_()
         Y = F.empty_fields(K, n, dtype)
         return lambda: F.fdbb_char_apply(dim, 0, 0, GAMMA, U, X, Y)
+    if op == "viscous_flux":
+        G = F.empty_fields(dim * dim, n, dtype).normal_()
+        gT = F.empty_fields(dim, n, dtype).normal_()
+        Fv = F.empty_fields(K * dim, n, dtype)
+        return lambda: F.fdbb_viscous_flux(dim, 1e-3, 2e-3, U, G, gT, Fv)
     if op == "eos_pvt":
         p, c, T = (torch.empty(n, dtype=dtype, device="cuda") for _ in range(3))
         return lambda: F.fdbb_eos_pvt(dim, 1, (4.4, 0.1, 2.5), U, p, c, T)
@@ -120,7 +125,7 @@ def bytes_per_point(op: str, dim: int, elem: int) -> int:
            "eos": K + 2, "v_mag2": dim + 2, "flux": K + K * dim, "flux_jacobian": K + dim * K * K,
            "riemann_invariants": K + 2 * dim + 1, "fused": K + K * dim + dim * K * K + 2 * dim + 1,
            "adjoint": K * K, "eigenvectors": K + 2 * dim * K * K, "char_apply": 3 * K,
-           "roe_average": 3 * K, "eos_pvt": K + 3}[op]
+           "roe_average": 3 * K, "eos_pvt": K + 3, "viscous_flux": K + dim * dim + dim + K * dim}[op]
     return per * elem
 
 
@@ -227,7 +232,7 @@ def main(argv=None):
                 n = (auto_size(op, dim, 8 if dt == "f64" else 4) if args.n == "auto" else int(args.n))
                 res = search(op, dim, dt, n, args.reps, verbose=args.verbose)
                 best_ms, (block, ppt, cap, nt) = res[0]
-                base = [ms for ms, cfg in res if cfg == (256, 1 if op in ("fused", "flux_jacobian") else
+                base = [ms for ms, cfg in res if cfg == (256, 1 if op in ("fused", "flux_jacobian", "viscous_flux") else
                                                          (2 if dt == "f64" else 4), 0, 1)]
                 entries[f"{op}/{dim}/{dt}"] = {"block": block, "ppt": ppt, "grid_cap": cap, "nt": nt,
                                                "ms": round(best_ms, 5), "n": n,

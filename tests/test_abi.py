@@ -155,6 +155,26 @@ def test_eos_pvt_checks():
     assert lib.fdbb_task_check(ctypes.byref(t)) == F.EINVAL
 
 
+def test_viscous_flux_checks():
+    lib = F.library()
+    C0 = 0x30000000
+    D0 = 0x40000000
+
+    def call(mu=0.1, kappa=0.1, dim=3, G=B0, out=D0, n=100):
+        return lib.fdbb_viscous_flux(dim, mu, kappa, 0, A0, 128, G, 128, C0, 128, out, 128, n, None)
+
+    assert call(mu=-1.0) == F.EINVAL
+    assert call(kappa=float("nan")) == F.EINVAL
+    assert call(dim=0) == F.EINVAL
+    assert call(G=None) == F.EINVAL
+    assert call(out=C0 + 8) == F.EALIAS  # output overlaps gradT
+    assert call(out=A0) == F.EALIAS  # no in-place form
+    t = F.Task()
+    t.op, t.dim, t.dtype, t.gamma, t.n = F.OPS["viscous_flux"], 3, 0, 1.4, 100
+    t.in0, t.ld_in0, t.out0, t.ld_out0 = A0, 128, D0, 128
+    assert lib.fdbb_task_check(ctypes.byref(t)) == F.EINVAL
+
+
 def test_server_rejects_bad_arguments():
     lib = F.library()
     h = ctypes.c_void_p()

@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_common import DTYPES, GAMMA, host, prim_states, require_gpu, states
+from gpu_common import DTYPES, GAMMA, NP, host, prim_states, require_gpu, states
 from metrics import (TOL, blocks_error, char_groups, flux_groups, group_error, riemann_groups, roe_error,
                      state_groups)
 from paper_1809_09851_amd import fdbb as F
@@ -281,6 +281,30 @@ def test_eos_pvt_partial_outputs():
     F.fdbb_eos_pvt(3, "stiffened_gas", (4.4, 0.3, 0.7), Ug, None, None, T)
     rT = oracle.eos_pvt(3, 1, (4.4, 0.3, 0.7), Uo)[2]
     assert group_error(host(T)[None], rT[None], [[0]]) <= TOL["f64"]
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("dim", DIMS)
+@pytest.mark.parametrize("n", SIZES)
+def test_viscous_flux(dim, dt, n):
+    Uo, Ug = states(dim, n, _seed(dim, n, dt, 23), dt)
+    rng = np.random.default_rng(_seed(dim, n, dt, 24))
+    G = rng.normal(size=(dim * dim, n)).astype(NP[dt]).astype(np.float64)
+    gT = rng.normal(size=(dim, n)).astype(NP[dt]).astype(np.float64)
+    Gg = F.to_fields(torch.from_numpy(G).to(DTYPES[dt]).cuda())
+    gTg = F.to_fields(torch.from_numpy(gT).to(DTYPES[dt]).cuda())
+    mu, kappa = 0.01, 0.02
+    Fv = F.viscous_flux(Ug, Gg, gTg, mu, kappa)
+    ref = oracle.viscous_flux(dim, mu, kappa, Uo, G, gT)
+    # stresses and energy fluxes are sums of signed terms: measure each
+    # direction against the size of its terms
+    K = dim + 2
+    v = np.abs(Uo[1:dim + 1] / Uo[0])
+    gabs = np.abs(G).max(axis=0)
+    den = mu * 4 * gabs * (1 + v.sum(axis=0)) + kappa * np.abs(gT).max(axis=0)
+    got = host(Fv)
+    assert np.all(got[[d for d in range(dim)]] == 0.0)  # mass row
+    assert group_error(got, ref, [[r * dim + d for r in range(1, K)] for d in range(dim)], denom=den) <= TOL[dt]
 
 
 # ------------------------------------------------------------ edge cases
