@@ -424,9 +424,9 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=1 << 24)
     ap.add_argument("--extras", action="store_true", help="also time the other building blocks")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--serve-rates", default="1000",
+    ap.add_argument("--serve-rates", default="100,300,1000,3000,10000",
                     help="comma-separated Poisson rates (req/s) for the serving measurement; '' skips it")
-    ap.add_argument("--serve-count", type=int, default=1000)
+    ap.add_argument("--serve-count", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-engine", choices=("native", "python", "both"), default="native",
