@@ -398,19 +398,24 @@ def bench_ops(steps: int, warmup: int, dims=(3,), dtypes=("f64", "f32")):
 
 
 def bench_probes(steps: int, warmup: int, gib: float = 4.0):
-    """What HBM delivers to plain streaming kernels: read, write, copy."""
+    """What HBM delivers to plain streaming kernels (read, write, copy of
+    16-byte accesses): with one access per thread over a grid covering the
+    buffer ("flat"), and as a grid-stride loop over 8 workgroups per compute
+    unit ("stride")."""
     import torch
     from paper_1809_09851_amd import fdbb as F
     nbytes = int(gib * (1 << 30))
     a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
-    sink = torch.empty(1 << 16, dtype=torch.int64, device="cuda")
+    flat = nbytes // 16 // 256
+    sink = torch.empty(max(flat, 1 << 16), dtype=torch.int64, device="cuda")
     res = {}
-    for name, moved, fn in (("read", nbytes, lambda: F.probe_read(a, sink)),
-                            ("write", nbytes, lambda: F.probe_write(b)),
-                            ("copy", 2 * nbytes, lambda: F.probe_copy(a, b))):
-        _, ev = timed_launches(fn, steps, warmup)
-        res[name] = round(moved / (ev * 1e-3) / 1e9, 1)
+    for form, grid in (("flat", flat), ("stride", 0)):
+        for name, moved, fn in (("read", nbytes, lambda: F.probe_read(a, sink, grid)),
+                                ("write", nbytes, lambda: F.probe_write(b, grid=grid)),
+                                ("copy", 2 * nbytes, lambda: F.probe_copy(a, b, grid))):
+            _, ev = timed_launches(fn, steps, warmup)
+            res[f"{name}_{form}"] = round(moved / (ev * 1e-3) / 1e9, 1)
     del a, b, sink
     torch.cuda.empty_cache()
     return res
