@@ -231,6 +231,10 @@ def main(argv=None):
             for dt in args.dtypes.split(","):
                 n = (auto_size(op, dim, 8 if dt == "f64" else 4) if args.n == "auto" else int(args.n))
                 res = search(op, dim, dt, n, args.reps, verbose=args.verbose)
+                if not res:
+                    print(f"fdbb: no usable configuration for {op}/{dim}/{dt} (all spill or are refused)",
+                          file=sys.stderr, flush=True)
+                    continue
                 best_ms, (block, ppt, cap, nt) = res[0]
                 base = [ms for ms, cfg in res if cfg == (256, 1 if op in ("fused", "flux_jacobian", "viscous_flux") else
                                                          (2 if dt == "f64" else 4), 0, 1)]

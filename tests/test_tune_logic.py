@@ -52,3 +52,15 @@ def test_table_round_trip(tmp_path, monkeypatch):
         assert F.fdbb_get_launch_config("fused", 3, F.F64) == oldf
     finally:
         F.fdbb_set_launch_config("flux", 3, F.F64, *old)
+
+
+def test_main_skips_an_op_with_no_usable_configuration(tmp_path, monkeypatch):
+    """When every configuration spills (or is refused), the tuner reports it
+    and writes no entry instead of failing."""
+    monkeypatch.setattr(tune, "search", lambda *a, **k: [])
+    monkeypatch.setattr(tune, "arch_key", lambda: "gfx950/hiptest")
+    monkeypatch.setattr(tune.torch.cuda, "set_device", lambda d: None)
+    out = tmp_path / "t.json"
+    assert tune.main(["--ops", "adjoint", "--dims", "3", "--dtypes", "f64", "--n", "1024",
+                      "--write", str(out)]) == 0
+    assert json.loads(out.read_text()) == {"gfx950/hiptest": {}}
