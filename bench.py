@@ -249,11 +249,13 @@ def bench_autograd(steps: int, warmup: int):
 
 
 def bench_serving(rates, count: int, warmup: int, slots: int = 8, batch_mb: float = 64.0,
-                  engine: str = "native", budget: int = 64 * 10 ** 9):
+                  engine: str = "native", budget: int = 200 * 10 ** 9):
     """Poisson request streams: continuous batching against one launch per
     request on a single stream (same requests, same pools), through the
     native server, the Python scheduler, or both."""
+    import torch
     from paper_1809_09851_amd import serve as S
+    torch.cuda.empty_cache()  # the native server takes its whole budget up front
     pools = S.StatePools()
     out = []
     engines = ("native", "python") if engine == "both" else (engine,)
