@@ -20,7 +20,9 @@
  * completes.  Tags identify requests from submission to release and must be
  * unique among them.  All calls return fdbb_status codes and are
  * thread-safe; results are unaffected by which other requests share a
- * launch.
+ * launch.  While launches are in flight the scheduler thread polls their
+ * events without sleeping (one host core); idle, it sleeps until a
+ * submission or a release.
  */
 #ifndef FDBB_SERVER_H
 #define FDBB_SERVER_H

@@ -117,3 +117,31 @@ def test_oversized_request_is_refused(pools):
         with pytest.raises(F.FdbbError):
             srv.submit(S.request_task(big), 0)
     srv.close()
+
+
+def test_tags_ops_and_releases_are_checked(pools):
+    reqs = _requests(pools, 2, 24)
+    srv = S.NativeServer(8 * 10 ** 9, slots=2)
+    t = S.request_task(reqs[0])
+    srv.submit(t, 7)
+    with pytest.raises(F.FdbbError):  # tag 7 is still in use
+        srv.submit(S.request_task(reqs[1]), 7)
+    bad = S.request_task(reqs[1])
+    bad.op = F.OPS["eigenvectors"]
+    with pytest.raises(F.FdbbError):  # not a batch op
+        srv.submit(bad, 8)
+    with pytest.raises(F.FdbbError):  # nothing completed under tag 9
+        srv.release(9)
+    done = []
+    t_end = time.time() + 30
+    while not done:
+        done = srv.poll()
+        assert time.time() < t_end
+    assert [c.tag for c in done] == [7] and done[0].status == 0
+    srv.release(7)
+    srv.submit(S.request_task(reqs[1]), 7)  # the tag is free again
+    while not srv.poll():
+        assert time.time() < t_end
+    srv.release(7)
+    assert srv.stats()["arena_bytes"] == 0
+    srv.close()
