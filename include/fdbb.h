@@ -9,7 +9,8 @@
  * Conservative state U = (rho, m_1..m_D, E): density, momentum rho v and
  * total energy per unit volume (the paper's "rho E"; Sec. 2.2, "Variables").
  * Primitive state V = (rho, v_1..v_D, p).  Perfect gas with adiabatic index
- * gamma = c_p / c_v > 1 (the paper's example: 7/2 over 5/2 = 1.4).
+ * gamma = c_p / c_v > 1 (the paper's example: 7/2 over 5/2 = 1.4); only the
+ * general EOS entry point (fdbb_eos_pvt) takes another equation of state.
  *
  * ---------------------------------------------------------------- layout
  * A "field set" is a device base pointer plus a leading dimension ld, in
@@ -27,7 +28,8 @@
  * ---------------------------------------------------------------- contract
  * Ownership: the caller owns every buffer; no entry point allocates or frees
  * memory, except the batch plans below, which own their descriptor tables
- * and graphs until destroyed.
+ * and graphs until destroyed (and the request server of fdbb_server.h,
+ * which owns its arena).
  * Streams: `stream` is a hipStream_t passed as void*, NULL for the default
  * stream.  Calls are asynchronous: they validate on the host, enqueue one
  * kernel on `stream` and return; results are ready when the stream reaches
@@ -40,7 +42,8 @@
  *   FDBB_EALIAS  any overlap between an input and an output field set, or
  *                between two outputs, except the exact in-place use (same
  *                base, same ld) allowed for the K -> K transforms
- *                (cons2prim, prim2cons, cons2char, char2cons).  In place,
+ *                (cons2prim, prim2cons, cons2char, char2cons, char_apply,
+ *                roe_average).  In place,
  *                cons2prim and prim2cons leave rho where it is and do not
  *                store it again (Sec. 2.2, "Variables": source and
  *                destination being the same costs no transfer of density);
