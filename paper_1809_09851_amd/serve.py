@@ -462,6 +462,51 @@ class NativeServer:
             pass
 
 
+class _DeviceArray:
+    """Server-owned device memory described for torch.as_tensor (the array
+    interface: pointer, shape, element type; C-contiguous)."""
+
+    def __init__(self, ptr: int, shape, elem: int):
+        self.__cuda_array_interface__ = {"data": (int(ptr), False), "shape": tuple(int(x) for x in shape),
+                                         "typestr": "<f8" if elem == 8 else "<f4", "version": 2,
+                                         "strides": None}
+
+
+def completion_outputs(c, op: str, dim: int, n: int, elem: int):
+    """Zero-copy tensors over a native completion's outputs in the server's
+    arena, in the layouts of the single-call entry points (fields (count, n),
+    blocks (D, n, K, K); the fused op gives (F, A, R), eos (p, c)).  They are
+    valid until the request is released."""
+    import torch
+    K = dim + 2
+    ld = int(c.ld)
+
+    def fields(ptr, count):
+        return torch.as_tensor(_DeviceArray(ptr, (count, ld), elem), device="cuda")[:, :n]
+
+    def blocks(ptr):
+        return torch.as_tensor(_DeviceArray(ptr, (dim, ld, K, K), elem), device="cuda")[:, :n]
+
+    def single(ptr):
+        return torch.as_tensor(_DeviceArray(ptr, (ld,), elem), device="cuda")[:n]
+
+    if op in ("cons2prim", "prim2cons", "cons2char", "char2cons", "adjoint", "roe_average"):
+        return (fields(c.out0, K),)
+    if op == "flux":
+        return (fields(c.out0, K * dim),)
+    if op == "riemann_invariants":
+        return (fields(c.out0, 2 * dim + 1),)
+    if op == "flux_jacobian":
+        return (blocks(c.out0),)
+    if op == "v_mag2":
+        return (single(c.out0),)
+    if op == "eos":
+        return (single(c.out0), single(c.out1))
+    if op == "fused":
+        return (fields(c.out0, K * dim), blocks(c.out1), fields(c.out2, 2 * dim + 1))
+    raise ValueError(op)
+
+
 def request_task(r: Request):
     """The fdbb_task of a request (outputs are placed by the server)."""
     from . import batch as B

@@ -145,3 +145,43 @@ def test_tags_ops_and_releases_are_checked(pools):
     srv.release(7)
     assert srv.stats()["arena_bytes"] == 0
     srv.close()
+
+
+def test_zero_copy_outputs_match_copies(pools):
+    """completion_outputs views the arena in place: equal to a copy of the
+    same memory, for single- and multi-output ops."""
+    reqs = _requests(pools, 12, 25)
+    srv = S.NativeServer(8 * 10 ** 9, slots=2, max_batch=8, max_batch_bytes=1e12)
+    got = {}
+    tasks = [S.request_task(r) for r in reqs]
+    for k, t in enumerate(tasks):
+        srv.submit(t, k)
+    t_end = time.time() + 60
+    while len(got) < len(reqs):
+        for c in srv.poll():
+            r = reqs[c.tag]
+            (view,) = S.completion_outputs(c, r.op, r.dim, r.n, r.elem)
+            copy = _fetch(r, c)
+            assert torch.equal(view, copy)
+            got[c.tag] = True
+            srv.release(c.tag)
+        assert time.time() < t_end
+    # a fused request: three outputs
+    U = pools.U[(3, 8)][:, :5000]
+    from paper_1809_09851_amd import batch as B
+    t = B._task("fused", 3, F.dtype_code(U.dtype), GAMMA, U.shape[1])
+    B._set(t, "in0", U, 5)
+    srv.submit(t, 99)
+    done = []
+    while not done:
+        done = srv.poll()
+        assert time.time() < t_end
+    Fv, A, R = S.completion_outputs(done[0], "fused", 3, U.shape[1], U.element_size())
+    Fr, Ar, Rr = F.euler_fused(U, GAMMA)
+    torch.cuda.synchronize()
+    tol = 1e-14 if U.element_size() == 8 else 1.2e-7
+    for a, b in ((Fv, Fr), (A, Ar), (R, Rr)):
+        den = b.abs().max().clamp_min(1e-300)
+        assert ((a - b).abs().max() / den).item() <= tol
+    srv.release(99)
+    srv.close()
