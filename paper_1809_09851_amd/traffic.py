@@ -9,8 +9,8 @@ of the kernel's sources; a record whose hash no longer matches the sources
 describes another kernel and is not used.
 
     python -m paper_1809_09851_amd.traffic --kernel k_fused \\
-        --fetch gpurun_out/pmc_fetch/fetch_counter_collection.csv \\
-        --write gpurun_out/pmc_write/write_counter_collection.csv \\
+        --fetch pmc_fetch/fetch_counter_collection.csv \\
+        --write pmc_write/write_counter_collection.csv \\
         --n 16777216 --out profiles/fused3d_f64_2p24_traffic.json
 """
 from __future__ import annotations
