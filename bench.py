@@ -5,8 +5,12 @@ Jacobians + Riemann invariants) on one MI355X, against the HBM roofline.
 
 One step is one fused pass over N = 2^24 points of a seeded synthetic 3D
 state (rho, p ~ U[0.5, 2], v_i ~ N(0, 0.5^2)), FP64 storage, inputs and
-outputs resident in HBM.  Prints one JSON line.  ``--extras`` adds the other
-building blocks (FP32 storage, single-op launches, 1D ops, adjoint).
+outputs resident in HBM.  Prints one JSON line with the roofline (HIP-event
+time, HBM traffic from the committed counter record), the CPU oracle's rate
+and the served p50/p99 latencies of the request server.  ``--extras`` adds
+the other building blocks (FP32 storage, the three-launch form, 1D ops,
+adjoint, autograd, batches, HBM probes, every single-op entry point);
+``--paper-sweeps`` the paper's two experiments over N = 2^10..2^28.
 """
 from __future__ import annotations
 

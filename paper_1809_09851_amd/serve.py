@@ -10,10 +10,14 @@ giving their bytes back to the budget.  Work of different slots overlaps on
 the device, so requests that arrive while others run are started as slots
 and memory free up.
 
-The scheduler is plain Python over an executor interface (allocate /
-launch / done), so its logic is tested on the CPU with a fake executor and a
-virtual clock; ``GpuBatchExecutor`` is the real one, ``SingleLaunchExecutor``
-the one-launch-per-request FIFO baseline on a single stream.
+Two implementations share these rules.  ``NativeServer`` drives the C++
+server of fdbb_server.h (scheduler thread, HBM arena, completion events
+polled without sleeping); ``native_serve_benchmark`` measures it.
+``Server`` is the same scheduler in plain Python over an executor interface
+(allocate / launch / done), so its logic is tested on the CPU with a fake
+executor and a virtual clock; ``GpuBatchExecutor`` is its GPU executor,
+``SingleLaunchExecutor`` the one-launch-per-request FIFO baseline on a
+single stream.
 """
 from __future__ import annotations
 
