@@ -601,8 +601,13 @@ __device__ __forceinline__ void tile_char2cons(const Args &a, int64_t tile0)
             vp[K - 1] = p;
 #pragma unroll
             for (int k = 0; k < D; ++k) {
+                // v_dir from the invariants; tangential k from slot 2 +
+                // (k < dir ? k : k - 1), picked with fixed indices (a
+                // runtime index would put w in scratch memory)
                 double vk = 0.5 * (wp + wm);
-                if (k != dir) vk = w[c][2 + (k < dir ? k : k - 1)][j];
+#pragma unroll
+                for (int slot = 0; slot < D - 1; ++slot)
+                    if (k != dir && (k < dir ? k : k - 1) == slot) vk = w[c][2 + slot][j];
                 vp[1 + k] = vk;
             }
             double uj[K];
