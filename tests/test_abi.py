@@ -227,3 +227,17 @@ def test_batch_plan_rejects_bad_tasks():
     assert lib.fdbb_batch_plan_create(t, 1, 0, 256, 1, 0, 1, ctypes.byref(plan)) == F.EINVAL
     assert lib.fdbb_batch_plan_create(t, 1, 1, 100, 1, 0, 1, ctypes.byref(plan)) == F.EINVAL
     assert not plan.value
+
+
+def test_headers_are_plain_c_and_cpp(tmp_path):
+    """The public headers compile as strict C99 and as C++11, so that a C
+    caller needs nothing but the headers and libfdbb.so."""
+    import subprocess
+    src = tmp_path / "use.c"
+    src.write_text('#include "fdbb.h"\n#include "fdbb_server.h"\n#include "fdbb_probe.h"\n'
+                   "int main(void) { return FDBB_OK; }\n")
+    inc = os.path.join(ROOT, "include")
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic", "-fsyntax-only",
+                    "-I", inc, str(src)], check=True)
+    subprocess.run(["g++", "-std=c++11", "-Wall", "-Wextra", "-Werror", "-fsyntax-only", "-I", inc,
+                    "-x", "c++", str(src)], check=True)
