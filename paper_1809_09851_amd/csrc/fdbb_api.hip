@@ -97,8 +97,9 @@ void init_configs()
         for (int d = 0; d < 3; ++d)
             for (int t = 0; t < 2; ++t) {
                 Config c;
-                // one point per thread where a point's registers are many
-                // (staged Jacobian blocks; the viscous flux's 2D + K*D fields)
+                // one point per thread where a point holds many registers
+                // (staged Jacobian blocks; the viscous flux's K + D*D + D
+                // input and K*D output fields)
                 const bool wide = (op == FDBB_OP_FLUX_JACOBIAN || op == FDBB_OP_FUSED || op == FDBB_OP_VISCOUS_FLUX);
                 c.block = 256;
                 c.ppt = wide ? 1 : (t == FDBB_F64 ? 2 : 4);
