@@ -743,7 +743,7 @@ const char *fdbb_status_string(int status)
 
 const char *fdbb_last_error(void) { return g_last_error.c_str(); }
 
-int fdbb_version(void) { return 100; }
+int fdbb_version(void) { return 200; }
 
 }  // extern "C"
 
