@@ -127,8 +127,15 @@ def cpu_baseline(n_sample: int = 1 << 24, seed: int = 1):
         oracle.flux_jacobian(3, GAMMA, U1)
         oracle.riemann_invariants(3, GAMMA, U1)
         best = min(best, time.perf_counter() - t0)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": round(passes * n_sample / wall / 1e9, 6), "unit": "Gpoints/s", "cores": threads,
-            "kind": "oracle", "single_core_value": round(n1 / best / 1e9, 6),
+            "kind": "oracle", "single_core_value": round(n1 / best / 1e9, 6), "cpu": model,
+            "host_cpus": os.cpu_count(),
             "sample": f"{passes} passes over the first {n_sample} points of the 3D N=2^24 workload "
                       f"(seed 1), fused flux+Jacobians+invariants, {threads} threads on disjoint "
                       f"2^14-point ranges, {wall:.2f} s wall"}
