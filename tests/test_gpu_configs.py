@@ -71,3 +71,40 @@ def _try_jac(Ug):
     except F.FdbbError as e:
         assert e.status == F.EINVAL
         return None
+
+
+@pytest.mark.parametrize("block,ppt,grid,nt", CONFIGS)
+def test_eigen_adjoint_roe_all_configs(block, ppt, grid, nt):
+    """The other LDS-staged kernel (eigenvector blocks) and the kernels with
+    two inputs (adjoint, Roe average) in every configuration."""
+    import numpy as np
+    from metrics import roe_error
+    from paper_1809_09851_amd import inputs
+    n = 3001
+    dim, K = 3, 5
+    for dt, code, es in (("f64", F.F64, 8), ("f32", F.F32, 4)):
+        Uo, Ug = states(dim, n, 90, dt)
+        cfg = (block, ppt, grid, nt)
+        try:
+            L, R = _with_config("eigenvectors", dim, code, cfg, lambda: F.eigenvectors(Ug, GAMMA))
+        except F.FdbbError as e:
+            # refused: more than 256 threads, or more LDS than a workgroup has
+            assert e.status == F.EINVAL and (block > 256 or block * ppt * K * K * es > 160 * 1024)
+        else:
+            Lo, Ro = oracle.eigenvectors(dim, GAMMA, Uo)
+            assert blocks_error(host(L), Lo) <= TOL[dt]
+            assert blocks_error(host(R), Ro) <= TOL[dt]
+        fb = inputs.cotangent(dim, n, 91).astype(np.float32 if dt == "f32" else np.float64)
+        import torch
+        Fbg = F.to_fields(torch.from_numpy(fb).cuda())
+        Ub = _with_config("adjoint", dim, code, cfg, lambda: F.flux_adjoint(Ug, Fbg, GAMMA))
+        fb = fb.astype(np.float64)
+        A = np.abs(oracle.flux_jacobian(dim, GAMMA, Uo))
+        den = np.zeros((K, n))
+        for d in range(dim):
+            den += np.einsum("nrc,rn->cn", A[d], np.abs(np.array([fb[q * dim + d] for q in range(K)])))
+        assert group_error(host(Ub), oracle.flux_adjoint(dim, -1, GAMMA, Uo, fb), [list(range(K))],
+                           denom=den.max(axis=0)) <= TOL[dt]
+        URo, URg = states(dim, n, 92, dt)
+        Uh = _with_config("roe_average", dim, code, cfg, lambda: F.roe_average(Ug, URg, GAMMA))
+        assert roe_error(host(Uh), oracle.roe_average(dim, GAMMA, Uo, URo), Uo, URo) <= TOL[dt]
