@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "../../include/fdbb.h"
+#include "free_list.hpp"
 
 namespace {
 
@@ -100,16 +101,17 @@ double moved_bytes(const fdbb_task &t)
     return per * n * es;
 }
 
-// First-fit allocator over one device arena, 256-byte granules.
+// One device allocation of the budget's size, carved by a first-fit free
+// list (free_list.hpp).
 class Arena {
 public:
-    static constexpr size_t kAlign = 256;
-
     int init(size_t bytes)
     {
-        size_ = (bytes + kAlign - 1) / kAlign * kAlign;
-        if (hipMalloc(&base_, size_) != hipSuccess) return FDBB_ENOMEM;
-        free_[0] = size_;
+        list_.reset(bytes);
+        if (hipMalloc(&base_, list_.size()) != hipSuccess) {
+            base_ = nullptr;
+            return FDBB_ENOMEM;
+        }
         return FDBB_OK;
     }
     void release_all()
@@ -118,47 +120,15 @@ public:
         base_ = nullptr;
     }
     // offset of a block of `bytes`, or SIZE_MAX when nothing fits
-    size_t alloc(size_t bytes)
-    {
-        bytes = std::max(kAlign, (bytes + kAlign - 1) / kAlign * kAlign);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                const size_t off = it->first, len = it->second;
-                free_.erase(it);
-                if (len > bytes) free_[off + bytes] = len - bytes;
-                used_ += bytes;
-                return off;
-            }
-        }
-        return SIZE_MAX;
-    }
-    void free(size_t off, size_t bytes)
-    {
-        bytes = std::max(kAlign, (bytes + kAlign - 1) / kAlign * kAlign);
-        used_ -= bytes;
-        auto it = free_.emplace(off, bytes).first;
-        auto next = std::next(it);
-        if (next != free_.end() && it->first + it->second == next->first) {
-            it->second += next->second;
-            free_.erase(next);
-        }
-        if (it != free_.begin()) {
-            auto prev = std::prev(it);
-            if (prev->first + prev->second == it->first) {
-                prev->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
+    size_t alloc(size_t bytes) { return list_.alloc(bytes); }
+    void free(size_t off, size_t bytes) { list_.release(off, bytes); }
     unsigned char *ptr(size_t off) const { return static_cast<unsigned char *>(base_) + off; }
-    size_t used() const { return used_; }
-    size_t size() const { return size_; }
+    size_t used() const { return list_.used(); }
+    size_t size() const { return list_.size(); }
 
 private:
     void *base_ = nullptr;
-    size_t size_ = 0;
-    size_t used_ = 0;
-    std::map<size_t, size_t> free_;  // offset -> length
+    fdbb::FreeList list_;
 };
 
 struct Request {
