@@ -410,6 +410,19 @@ def bench_ops(steps: int, warmup: int, dims=(3,), dtypes=("f64", "f32")):
     return out
 
 
+def write_ceiling(gib: float = 4.0, steps: int = 10, warmup: int = 3) -> float:
+    """GB/s of the plain write probe (16-byte non-temporal stores, one per
+    thread, over a grid covering the buffer)."""
+    import torch
+    from paper_1809_09851_amd import fdbb as F
+    nbytes = int(gib * (1 << 30))
+    b = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    _, ev = timed_launches(lambda: F.probe_write(b, grid=nbytes // 16 // 256), steps, warmup)
+    del b
+    torch.cuda.empty_cache()
+    return nbytes / (ev * 1e-3) / 1e9
+
+
 def bench_probes(steps: int, warmup: int, gib: float = 4.0):
     """What HBM delivers to plain streaming kernels (read, write, copy of
     16-byte accesses): with one access per thread over a grid covering the
@@ -496,6 +509,11 @@ def main(argv=None):
                      "traffic": traffic,
                      "bytes_per_point": fused_bytes(3, 8), "kernel_ms": round(main_run["kernel_ms"], 4)},
     }
+    # the device's own ceiling for a plain write stream (95 % of the fused
+    # pass's bytes are writes), measured in the same process
+    ceiling = write_ceiling()
+    line["roofline"]["measured_write_ceiling_gbs"] = round(ceiling, 1)
+    line["roofline"]["frac_of_measured_ceiling"] = round(achieved / ceiling, 4)
     if args.extras:
         ex = {}
         f32 = bench_fused(args.n, args.steps, args.warmup, torch.float32, "3d_f32_fused")
