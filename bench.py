@@ -423,6 +423,21 @@ def write_ceiling(gib: float = 4.0, steps: int = 10, warmup: int = 3) -> float:
     return nbytes / (ev * 1e-3) / 1e9
 
 
+def bench_fused_stores(steps: int, warmup: int, n: int = 1 << 24):
+    """GB/s of the fused 3D pass's stores alone (constant values in its
+    layout, order and tiling; no loads, no arithmetic): the ceiling of its
+    store pattern on this device."""
+    import torch
+    from paper_1809_09851_amd import fdbb as F
+    Fo = torch.empty((15, n), dtype=torch.float64, device="cuda")
+    R = torch.empty((7, n), dtype=torch.float64, device="cuda")
+    A = torch.empty((3, n, 5, 5), dtype=torch.float64, device="cuda")
+    _, ev = timed_launches(lambda: F.probe_fused_stores(Fo, R, A, n), steps, warmup)
+    del Fo, R, A
+    torch.cuda.empty_cache()
+    return round(776 * n / (ev * 1e-3) / 1e9, 1)
+
+
 def bench_probes(steps: int, warmup: int, gib: float = 4.0):
     """What HBM delivers to plain streaming kernels (read, write, copy of
     16-byte accesses): with one access per thread over a grid covering the
@@ -528,6 +543,7 @@ def main(argv=None):
         ex["batched_512_f64"] = bench_batched(5, 2, torch.float64)
         ex["batched_512_f32"] = bench_batched(5, 2, torch.float32)
         ex["hbm_probes_gbs"] = bench_probes(max(10, args.steps // 5), 3)
+        ex["fused_store_pattern_gbs"] = bench_fused_stores(max(10, args.steps // 5), 3)
         ex["single_ops_2gb"] = bench_ops(max(10, args.steps // 5), 3)
         line["extras"] = ex
     if args.paper_sweeps:

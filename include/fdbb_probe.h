@@ -30,6 +30,16 @@ int fdbb_probe_write(void *dst, int64_t bytes, uint64_t pattern, int grid, void 
  * caller provides at least `grid` elements); reads `bytes`. */
 int fdbb_probe_read(const void *src, int64_t bytes, uint64_t *sink, int grid, void *stream);
 
+/* The 3D fused pass's stores without its loads or arithmetic: constant
+ * values written in the fused kernel's output layout and store order
+ * (flux tensor F, 15 fields of n; Riemann invariants R, 7 fields of n;
+ * Jacobian blocks A, 3 x n blocks of 25 doubles; all with ld = n), with its
+ * tiling (128 threads per workgroup, 4 points per thread, each wave storing
+ * its 256 points' F and R chunk by chunk, then its blocks one direction at a
+ * time).  Writes 776 bytes per point.  n must be a positive multiple of 512
+ * (FDBB_EINVAL otherwise); the arrays are FP64 and 16-byte aligned. */
+int fdbb_probe_fused_stores(double *F, double *R, double *A, int64_t n, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -44,6 +44,28 @@ __global__ __launch_bounds__(256) void k_read(const u64x2 *__restrict__ src, int
     if (threadIdx.x == 0) sink[blockIdx.x] = part[0];
 }
 
+// The fused 3D pass's store pattern with constant values: 256 points per
+// wave, two waves per workgroup; F and R chunk by chunk (two chunks of 128
+// points, 16 bytes per lane), then each direction's 256 blocks as 50
+// lane-contiguous 1 KB stores.
+__global__ __launch_bounds__(128) void k_fused_stores(double *__restrict__ F, double *__restrict__ R,
+                                                      double *__restrict__ A, int64_t n)
+{
+    using d2 = double __attribute__((ext_vector_type(2)));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t wave0 = (int64_t)blockIdx.x * 512 + wave * 256;
+    const d2 v = {1.0, 2.0};
+    for (int c = 0; c < 2; ++c)
+        for (int f = 0; f < 22; ++f) {
+            double *base = f < 15 ? F + (int64_t)f * n : R + (int64_t)(f - 15) * n;
+            __builtin_nontemporal_store(v, reinterpret_cast<d2 *>(base + wave0 + c * 128 + lane * 2));
+        }
+    for (int d = 0; d < 3; ++d) {
+        d2 *base = reinterpret_cast<d2 *>(A + ((int64_t)d * n + wave0) * 25);
+        for (int k = 0; k < 50; ++k) __builtin_nontemporal_store(v, base + k * 64 + lane);
+    }
+}
+
 int grid_for(int grid)
 {
     if (grid > 0) return grid;
@@ -89,6 +111,13 @@ int fdbb_probe_read(const void *src, int64_t bytes, uint64_t *sink, int grid, vo
     if (g <= 0) return FDBB_EHIP;
     hipLaunchKernelGGL(k_read, dim3(g), dim3(256), 0, (hipStream_t)stream, (const u64x2 *)src, bytes / 16,
                        (unsigned long long *)sink);
+    return hipGetLastError() == hipSuccess ? FDBB_OK : FDBB_EHIP;
+}
+
+int fdbb_probe_fused_stores(double *F, double *R, double *A, int64_t n, void *stream)
+{
+    if (!aligned(F) || !aligned(R) || !aligned(A) || n <= 0 || n % 512) return FDBB_EINVAL;
+    hipLaunchKernelGGL(k_fused_stores, dim3((unsigned)(n / 512)), dim3(128), 0, (hipStream_t)stream, F, R, A, n);
     return hipGetLastError() == hipSuccess ? FDBB_OK : FDBB_EHIP;
 }
 

@@ -120,6 +120,7 @@ def library():
         lib.fdbb_probe_copy.argtypes = [_p, _p, _i64, _i, _p]
         lib.fdbb_probe_write.argtypes = [_p, _i64, ctypes.c_uint64, _i, _p]
         lib.fdbb_probe_read.argtypes = [_p, _i64, _p, _i, _p]
+        lib.fdbb_probe_fused_stores.argtypes = [_p, _p, _p, _i64, _p]
         _lib = lib
         if os.environ.get("FDBB_NO_TUNED_TABLE") != "1":
             from . import tune
@@ -465,6 +466,12 @@ def probe_copy(src: torch.Tensor, dst: torch.Tensor, grid: int = 0, stream=None)
 def probe_write(dst: torch.Tensor, pattern: int = 0x3FF0000000000000, grid: int = 0, stream=None):
     nbytes = dst.numel() * dst.element_size()
     check(library().fdbb_probe_write(dst.data_ptr(), nbytes // 16 * 16, pattern, grid, _stream(stream)))
+
+
+def probe_fused_stores(F_: torch.Tensor, R: torch.Tensor, A: torch.Tensor, n: int, stream=None):
+    """The fused 3D pass's stores alone (constant values, same layout and
+    order): F (15, n), R (7, n), A (3, n, 5, 5), FP64, n a multiple of 512."""
+    check(library().fdbb_probe_fused_stores(F_.data_ptr(), R.data_ptr(), A.data_ptr(), n, _stream(stream)))
 
 
 def probe_read(src: torch.Tensor, sink: torch.Tensor, grid: int = 0, stream=None):

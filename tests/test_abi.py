@@ -229,6 +229,13 @@ def test_batch_plan_rejects_bad_tasks():
     assert not plan.value
 
 
+def test_fused_store_probe_checks():
+    lib = F.library()
+    assert lib.fdbb_probe_fused_stores(A0, B0, A0 + (1 << 30), 1000, None) == F.EINVAL  # not a multiple of 512
+    assert lib.fdbb_probe_fused_stores(A0 + 8, B0, A0 + (1 << 30), 1024, None) == F.EINVAL  # misaligned
+    assert lib.fdbb_probe_fused_stores(A0, B0, A0 + (1 << 30), 0, None) == F.EINVAL
+
+
 def test_headers_are_plain_c_and_cpp(tmp_path):
     """The public headers compile as strict C99 and as C++11, so that a C
     caller needs nothing but the headers and libfdbb.so."""
