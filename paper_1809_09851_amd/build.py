@@ -26,8 +26,8 @@ FLAGS = [
     "-fPIC",
     "-Wall",
     "-Wno-unused-function",
-    # Packed FP32 instructions stay off: hand-free float code must not be
-    # turned into v_pk_* forms.
+    # Packed FP32 instructions stay off: the compiler must not turn ordinary
+    # float code into v_pk_* forms.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     f"-I{os.path.join(HERE, os.pardir, 'include')}",
 ]
