@@ -4,14 +4,14 @@
 
 namespace fdbb {
 
-template <int D, typename T, int P, bool NT>
+template <int D, typename T, int P, int NT>
 __global__ __launch_bounds__(1024) void k_adjoint(Args a, int64_t ntiles)
 {
     const int64_t tile_pts = (int64_t)blockDim.x * P;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) tile_adjoint<D, T, P, NT>(a, t * tile_pts);
 }
 
-template <int D, typename T, bool NT>
+template <int D, typename T, int NT>
 static const void *pick_p(int ppt)
 {
     switch (ppt) {
@@ -25,7 +25,7 @@ static const void *pick_p(int ppt)
 template <int D, typename T>
 static const void *pick_p(int ppt, bool nt)
 {
-    return nt ? pick_p<D, T, true>(ppt) : pick_p<D, T, false>(ppt);
+    return nt ? pick_p<D, T, kStoreNT>(ppt) : pick_p<D, T, kStoreRegular>(ppt);
 }
 
 const void *kernel_adjoint(int dim, int dtype, int ppt, bool nt)

@@ -7,7 +7,7 @@
 
 namespace fdbb {
 
-template <int D, typename T, int P, bool NT>
+template <int D, typename T, int P, int NT>
 __device__ __forceinline__ void run_tile(int op, const Args &a, int64_t tile0, unsigned char *smem)
 {
     switch (op) {
@@ -27,7 +27,7 @@ __device__ __forceinline__ void run_tile(int op, const Args &a, int64_t tile0, u
     }
 }
 
-template <int P, bool NT>
+template <int P, int NT>
 __global__ __launch_bounds__(kMaxBlockStaged) void k_batch(const TaskDev *__restrict__ tasks,
                                                 const int64_t *__restrict__ prefix,
                                                 const int64_t *__restrict__ header)
@@ -60,9 +60,11 @@ __global__ __launch_bounds__(kMaxBlockStaged) void k_batch(const TaskDev *__rest
 const void *kernel_batch(int ppt, bool nt)
 {
     switch (ppt) {
-    case 1: return nt ? (const void *)&k_batch<1, true> : (const void *)&k_batch<1, false>;
-    case 2: return nt ? (const void *)&k_batch<2, true> : (const void *)&k_batch<2, false>;
-    case 4: return nt ? (const void *)&k_batch<4, true> : (const void *)&k_batch<4, false>;
+    // streaming stores with nt alone: the persistent launch measured slower
+    // with nt + sc1 (1-7 %), unlike the single-launch fused kernel
+    case 1: return nt ? (const void *)&k_batch<1, kStoreNT> : (const void *)&k_batch<1, kStoreRegular>;
+    case 2: return nt ? (const void *)&k_batch<2, kStoreNT> : (const void *)&k_batch<2, kStoreRegular>;
+    case 4: return nt ? (const void *)&k_batch<4, kStoreNT> : (const void *)&k_batch<4, kStoreRegular>;
     default: return nullptr;
     }
 }

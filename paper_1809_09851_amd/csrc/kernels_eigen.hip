@@ -5,7 +5,7 @@
 
 namespace fdbb {
 
-template <int D, typename T, int P, bool NT>
+template <int D, typename T, int P, int NT>
 __global__ __launch_bounds__(kMaxBlockStaged) void k_eigen(Args a, int64_t ntiles)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -14,14 +14,14 @@ __global__ __launch_bounds__(kMaxBlockStaged) void k_eigen(Args a, int64_t ntile
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) tile_eigen<D, T, P, NT>(a, t * tile_pts, lds);
 }
 
-template <int D, typename T, int P, bool NT>
+template <int D, typename T, int P, int NT>
 __global__ __launch_bounds__(1024) void k_char_apply(Args a, int64_t ntiles)
 {
     const int64_t tile_pts = (int64_t)blockDim.x * P;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) tile_char_apply<D, T, P, NT>(a, t * tile_pts);
 }
 
-template <int FAM, int D, typename T, bool NT>
+template <int FAM, int D, typename T, int NT>
 static const void *pick_p(int ppt)
 {
     if constexpr (FAM == kFamEigen) {
@@ -44,7 +44,9 @@ static const void *pick_p(int ppt)
 template <int FAM, int D, typename T>
 static const void *pick_p(int ppt, bool nt)
 {
-    return nt ? pick_p<FAM, D, T, true>(ppt) : pick_p<FAM, D, T, false>(ppt);
+    // eigenvector blocks stream with nt + sc1, the products with nt
+    constexpr int streaming = FAM == kFamEigen ? kStoreNTSc1 : kStoreNT;
+    return nt ? pick_p<FAM, D, T, streaming>(ppt) : pick_p<FAM, D, T, kStoreRegular>(ppt);
 }
 
 template <int FAM>

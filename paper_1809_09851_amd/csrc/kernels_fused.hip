@@ -5,7 +5,7 @@
 
 namespace fdbb {
 
-template <int D, typename T, int P, bool NT>
+template <int D, typename T, int P, int NT>
 __global__ __launch_bounds__(kMaxBlockStaged) void k_fused(Args a, int64_t ntiles)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -15,7 +15,7 @@ __global__ __launch_bounds__(kMaxBlockStaged) void k_fused(Args a, int64_t ntile
         tile_fused<D, T, P, NT>(a, t * tile_pts, lds);
 }
 
-template <int D, typename T, bool NT>
+template <int D, typename T, int NT>
 static const void *pick_p(int ppt)
 {
     switch (ppt) {
@@ -29,7 +29,7 @@ static const void *pick_p(int ppt)
 template <int D, typename T>
 static const void *pick_p(int ppt, bool nt)
 {
-    return nt ? pick_p<D, T, true>(ppt) : pick_p<D, T, false>(ppt);
+    return nt ? pick_p<D, T, kStoreNTSc1>(ppt) : pick_p<D, T, kStoreRegular>(ppt);
 }
 
 const void *kernel_fused(int dim, int dtype, int ppt, bool nt)

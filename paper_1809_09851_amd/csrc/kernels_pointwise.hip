@@ -7,7 +7,7 @@
 
 namespace fdbb {
 
-template <int FAM, int D, typename T, int P, bool NT>
+template <int FAM, int D, typename T, int P, int NT>
 __global__ __launch_bounds__(1024) void k_pointwise(Args a, int64_t ntiles)
 {
     const int64_t tile_pts = (int64_t)blockDim.x * P;
@@ -25,7 +25,7 @@ __global__ __launch_bounds__(1024) void k_pointwise(Args a, int64_t ntiles)
     }
 }
 
-template <int FAM, int D, typename T, bool NT>
+template <int FAM, int D, typename T, int NT>
 static const void *pick_p(int ppt)
 {
     switch (ppt) {
@@ -39,7 +39,7 @@ static const void *pick_p(int ppt)
 template <int FAM, int D, typename T>
 static const void *pick_p(int ppt, bool nt)
 {
-    return nt ? pick_p<FAM, D, T, true>(ppt) : pick_p<FAM, D, T, false>(ppt);
+    return nt ? pick_p<FAM, D, T, kStoreNT>(ppt) : pick_p<FAM, D, T, kStoreRegular>(ppt);
 }
 
 template <int FAM>

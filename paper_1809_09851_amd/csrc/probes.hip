@@ -1,10 +1,13 @@
 // Streaming probes (declared in include/fdbb_probe.h): grid-stride loops of
 // 16-byte accesses, 256 threads per workgroup.  grid <= 0 launches 8
-// workgroups per compute unit.
+// workgroups per compute unit.  Stores are the streaming stores of the
+// fused kernel (nt + sc1, fdbb::put<kStoreNTSc1>).
 #include "../../include/fdbb.h"
 #include "../../include/fdbb_probe.h"
 
 #include <hip/hip_runtime.h>
+
+#include "euler_tiles.hpp"
 
 namespace {
 
@@ -14,7 +17,7 @@ __global__ __launch_bounds__(256) void k_copy(const u64x2 *__restrict__ src, u64
                                               int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        __builtin_nontemporal_store(src[i], dst + i);
+        fdbb::put<fdbb::kStoreNTSc1, u64x2>(dst + i, src[i]);
 }
 
 __global__ __launch_bounds__(256) void k_write(u64x2 *__restrict__ dst, int64_t n, unsigned long long pat)
@@ -23,7 +26,7 @@ __global__ __launch_bounds__(256) void k_write(u64x2 *__restrict__ dst, int64_t 
     v.x = pat;
     v.y = pat;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        __builtin_nontemporal_store(v, dst + i);
+        fdbb::put<fdbb::kStoreNTSc1, u64x2>(dst + i, v);
 }
 
 __global__ __launch_bounds__(256) void k_read(const u64x2 *__restrict__ src, int64_t n,
@@ -58,11 +61,11 @@ __global__ __launch_bounds__(128) void k_fused_stores(double *__restrict__ F, do
     for (int c = 0; c < 2; ++c)
         for (int f = 0; f < 22; ++f) {
             double *base = f < 15 ? F + (int64_t)f * n : R + (int64_t)(f - 15) * n;
-            __builtin_nontemporal_store(v, reinterpret_cast<d2 *>(base + wave0 + c * 128 + lane * 2));
+            fdbb::put<fdbb::kStoreNTSc1, d2>(reinterpret_cast<d2 *>(base + wave0 + c * 128 + lane * 2), v);
         }
     for (int d = 0; d < 3; ++d) {
         d2 *base = reinterpret_cast<d2 *>(A + ((int64_t)d * n + wave0) * 25);
-        for (int k = 0; k < 50; ++k) __builtin_nontemporal_store(v, base + k * 64 + lane);
+        for (int k = 0; k < 50; ++k) fdbb::put<fdbb::kStoreNTSc1, d2>(base + k * 64 + lane, v);
     }
 }
 
