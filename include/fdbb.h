@@ -233,7 +233,10 @@ int fdbb_viscous_flux(int dim, double mu, double kappa, int dtype, const void *U
  * fused pass, whose kernels stage blocks in LDS), `ppt` points per thread
  * (1, 2 or 4), `grid_cap` the largest grid (0 = one tile per workgroup;
  * otherwise workgroups loop over tiles) and `nontemporal` (1: outputs are
- * written with non-temporal stores, 0: regular stores).  Returns
+ * written with streaming stores, 0: regular stores; a streaming store sets
+ * the nt cache-policy bit, and in the kernels that write K x K blocks in
+ * one launch (fused pass, flux Jacobian, eigenvector blocks) also sc1, the
+ * device-scope bit).  Returns
  * FDBB_EINVAL for values outside these sets.  The table is process-wide and
  * safe to update while other threads launch. */
 int fdbb_set_launch_config(int op, int dim, int dtype, int block, int ppt, int grid_cap,
@@ -291,7 +294,7 @@ typedef struct fdbb_batch_plan fdbb_batch_plan;
  * The plan owns a device copy of the task table, the tile prefix sums and a
  * HIP graph holding one persistent kernel with `grid` workgroups of `block`
  * threads (64..256; grid 0 picks one sized to the device), `ppt` points per thread
- * and non-temporal (1) or regular (0) output stores.  Tasks that overlap
+ * and streaming (1: the nt bit) or regular (0) output stores.  Tasks that overlap
  * one another's outputs are rejected (FDBB_EALIAS).  Jacobian staging needs
  * LDS; a plan holds what its first task list needs, or, when created with
  * ntasks == 0, what any task needs (later task lists needing more than the
