@@ -51,21 +51,33 @@ struct Chunk {
     static constexpr int N = P / W;
 };
 
+// One load, regular or non-temporal (NTL: the nt bit, no normal cache
+// allocation).  The kernels that read two input field sets (adjoint, Roe
+// average, products with L or R) load with nt: timed alternately in one
+// process on the same buffers, that made them 5-8 % faster in 3D FP64,
+// while the single-input kernels (flux, fused pass) were 2-3 % slower.
+template <bool NTL, typename V>
+__device__ __forceinline__ V get(const V *p)
+{
+    if constexpr (NTL) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 // Load the W consecutive values at p (cnt of them valid) widened to FP64.
-template <typename T, int W>
+template <typename T, int W, bool NTL = false>
 __device__ __forceinline__ void load_chunk(const T *__restrict__ p, int cnt, bool vec, double *x)
 {
     if (vec && cnt == W) {
         if constexpr (W == 1) {
-            x[0] = (double)p[0];
+            x[0] = (double)get<NTL, T>(p);
         } else {
-            const vec_t<T, W> v = *reinterpret_cast<const vec_t<T, W> *>(p);
+            const vec_t<T, W> v = get<NTL, vec_t<T, W>>(reinterpret_cast<const vec_t<T, W> *>(p));
 #pragma unroll
             for (int j = 0; j < W; ++j) x[j] = (double)v[j];
         }
     } else {
 #pragma unroll
-        for (int j = 0; j < W; ++j) x[j] = (j < cnt) ? (double)p[j] : 1.0;
+        for (int j = 0; j < W; ++j) x[j] = (j < cnt) ? (double)get<NTL, T>(p + j) : 1.0;
     }
 }
 
@@ -168,20 +180,22 @@ struct Lane {
     // Position, inside the wave's 64 * P points, of the thread's point j.
     __device__ __forceinline__ int local(int j) const { return (j / W) * CS + lane * W + (j % W); }
 
-    // Chunk c (W values) of field `field` of a field set with row stride ld.
+    // Chunk c (W values) of field `field` of a field set with row stride ld
+    // (NTL: non-temporal loads).
+    template <bool NTL = false>
     __device__ __forceinline__ void load(const void *base, int64_t ld, int field, int c, double *x) const
     {
         const T *b = static_cast<const T *>(base) + i + (int64_t)field * ld + c * CS;
-        load_chunk<T, W>(b, count(c), vec, x);
+        load_chunk<T, W, NTL>(b, count(c), vec, x);
     }
 
     // Chunk c of `FIELDS` consecutive fields into x[field][W].
-    template <int FIELDS>
+    template <int FIELDS, bool NTL = false>
     __device__ __forceinline__ void load_fields(const void *base, int64_t ld, int c,
                                                 double (&x)[FIELDS][W]) const
     {
 #pragma unroll
-        for (int k = 0; k < FIELDS; ++k) load(base, ld, k, c, x[k]);
+        for (int k = 0; k < FIELDS; ++k) load<NTL>(base, ld, k, c, x[k]);
     }
 
     __device__ __forceinline__ void store(void *base, int64_t ld, int field, int c, const double *x) const
@@ -278,7 +292,7 @@ __device__ __forceinline__ void tile_roe(const Args &a, int64_t tile0)
             for (int k = 0; k <= D; ++k) sum[j][k] = 0.0;
         {
             double u[K][W];
-            L.template load_fields<K>(a.in0, a.ld_in0, c, u);
+            L.template load_fields<K, true>(a.in0, a.ld_in0, c, u);
 #pragma unroll
             for (int j = 0; j < W; ++j) {
                 double uj[K];
@@ -291,7 +305,7 @@ __device__ __forceinline__ void tile_roe(const Args &a, int64_t tile0)
         __builtin_amdgcn_sched_barrier(0);
         {
             double u[K][W];
-            L.template load_fields<K>(a.in1, a.ld_in1, c, u);
+            L.template load_fields<K, true>(a.in1, a.ld_in1, c, u);
 #pragma unroll
             for (int j = 0; j < W; ++j) {
                 double uj[K];
@@ -663,7 +677,7 @@ __device__ __forceinline__ void tile_adjoint(const Args &a, int64_t tile0)
     if (!L.any()) return;
     double u[NC][K][W];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) L.template load_fields<K>(a.in0, a.ld_in0, c, u[c]);
+    for (int c = 0; c < NC; ++c) L.template load_fields<K, true>(a.in0, a.ld_in0, c, u[c]);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         State<D> s[W];
@@ -684,7 +698,7 @@ __device__ __forceinline__ void tile_adjoint(const Args &a, int64_t tile0)
             if (a.dir >= 0 && d != a.dir) continue;
             double f[K][W];
 #pragma unroll
-            for (int r = 0; r < K; ++r) L.load(a.in1, a.ld_in1, a.dir < 0 ? r * D + d : r, c, f[r]);
+            for (int r = 0; r < K; ++r) L.template load<true>(a.in1, a.ld_in1, a.dir < 0 ? r * D + d : r, c, f[r]);
 #pragma unroll
             for (int j = 0; j < W; ++j) {
                 double fj[K], uj[K];
@@ -876,8 +890,8 @@ __device__ __forceinline__ void tile_char_apply(const Args &a, int64_t tile0)
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         double u[K][W], x[K][W], y[K][W];
-        L.template load_fields<K>(a.in0, a.ld_in0, c, u);
-        L.template load_fields<K>(a.in1, a.ld_in1, c, x);
+        L.template load_fields<K, true>(a.in0, a.ld_in0, c, u);
+        L.template load_fields<K, true>(a.in1, a.ld_in1, c, x);
 #pragma unroll
         for (int j = 0; j < W; ++j) {
             double uj[K];
