@@ -36,10 +36,26 @@ static const void *pick_p(int ppt)
     }
 }
 
+// Streaming store flavour per family and storage type: nt + sc1 where it
+// measured faster than nt alone, timed alternately in one process on the
+// same buffers (3D, a 2 GB working set: cons2prim and prim2cons FP64 by
+// 3.8 and 2.3 %, flux 2.0 / 4.2 %, Riemann invariants 2.0 / 7.6 %, |v|^2
+// FP32 3.8 %), nt elsewhere (the viscous flux FP64 ran 7 % slower with sc1,
+// cons2prim and prim2cons FP32 2-3 %).
+template <int FAM, typename T>
+constexpr int streaming_mode()
+{
+    constexpr bool f64 = sizeof(T) == 8;
+    if constexpr (FAM == kFamFlux || FAM == kFamRiemann) return kStoreNTSc1;
+    else if constexpr ((FAM == kFamCons2Prim || FAM == kFamPrim2Cons) && f64) return kStoreNTSc1;
+    else if constexpr (FAM == kFamVmag2 && !f64) return kStoreNTSc1;
+    else return kStoreNT;
+}
+
 template <int FAM, int D, typename T>
 static const void *pick_p(int ppt, bool nt)
 {
-    return nt ? pick_p<FAM, D, T, kStoreNT>(ppt) : pick_p<FAM, D, T, kStoreRegular>(ppt);
+    return nt ? pick_p<FAM, D, T, streaming_mode<FAM, T>()>(ppt) : pick_p<FAM, D, T, kStoreRegular>(ppt);
 }
 
 template <int FAM>
