@@ -86,13 +86,14 @@ __device__ __forceinline__ void load_chunk(const T *__restrict__ p, int cnt, boo
 //   kStoreNT:      non-temporal stores (the nt bit: streamed past the
 //                  caches' normal allocation);
 //   kStoreNTSc1:   nt plus sc1 (the device-scope coherence bit).
-// The launch configuration chooses between regular and streaming stores.
+// The launch configuration chooses between regular and streaming stores;
+// each kernel family's picker fixes which streaming flavour it uses, from
+// timings of both taken alternately in one process on the same buffers.
 // The single-launch kernels that write K x K blocks (fused pass, flux
 // Jacobian, eigenvector blocks) stream with nt + sc1, under which they ran
-// 1.8-3.5 % faster on this device than with nt alone, timed alternately in
-// one process (a plain write stream: 7.0 against 6.7-6.8 TB/s); the other
-// kernels, the persistent batch kernel among them, stream with nt, which
-// measured as well or better for them.
+// 1.8-3.5 % faster on this device than with nt alone (a plain write
+// stream: 7.0 against 6.7-6.8 TB/s); the persistent batch kernel streams
+// with nt, which measured faster for it.
 enum : int { kStoreRegular = 0, kStoreNT = 1, kStoreNTSc1 = 2 };
 
 // No compiler builtin sets sc1 on a global store, hence the inline
