@@ -234,9 +234,9 @@ int fdbb_viscous_flux(int dim, double mu, double kappa, int dtype, const void *U
  * (1, 2 or 4), `grid_cap` the largest grid (0 = one tile per workgroup;
  * otherwise workgroups loop over tiles) and `nontemporal` (1: outputs are
  * written with streaming stores, 0: regular stores; a streaming store sets
- * the nt cache-policy bit, and in the kernels that write K x K blocks in
- * one launch (fused pass, flux Jacobian, eigenvector blocks) also sc1, the
- * device-scope bit).  Returns
+ * the nt cache-policy bit, and in the fused pass, flux Jacobian,
+ * eigenvector blocks, flux and Riemann invariants, in FP64 cons2prim and
+ * prim2cons and in FP32 |v|^2 also sc1, the device-scope bit).  Returns
  * FDBB_EINVAL for values outside these sets.  The table is process-wide and
  * safe to update while other threads launch. */
 int fdbb_set_launch_config(int op, int dim, int dtype, int block, int ppt, int grid_cap,
