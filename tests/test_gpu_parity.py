@@ -340,6 +340,50 @@ def test_unpadded_and_offset_views(dim, dt):
 
 @pytest.mark.parametrize("dt", DTS)
 @pytest.mark.parametrize("dim", DIMS)
+def test_scalar_path_equals_vector_path(dim, dt):
+    """Inputs one element off alignment make every load and store of a call
+    take the scalar path (4- and 8-byte accesses, in every store and load
+    flavour the kernels use); the per-point arithmetic is shared, so each
+    result must equal, bit for bit, the 16-byte path's on an aligned copy of
+    the same data."""
+    from paper_1809_09851_amd import inputs
+    n = 1001
+    K = dim + 2
+    npdt = np.float32 if dt == "f32" else np.float64
+
+    def pair(a):
+        tight = torch.from_numpy(np.ascontiguousarray(a, dtype=npdt)).cuda()
+        view = tight[:, 1:]                      # base one element past a 16-byte boundary
+        return view, F.to_fields(view)           # unaligned view, padded aligned copy
+
+    Uo, _ = states(dim, n + 1, 23, dt)
+    URo, _ = states(dim, n + 1, 24, dt)
+    Uu, Ua = pair(Uo)
+    URu, URa = pair(URo)
+    Fbu, Fba = pair(inputs.cotangent(dim, n + 1, 25))
+    Xu, Xa = pair(inputs.cotangent(dim, n + 1, 26, fields=K))
+    Vu, Va = pair(host(F.cons2prim(Ua, GAMMA)))
+    assert Uu.data_ptr() % 16 != 0 and Ua.data_ptr() % 16 == 0
+
+    def same(name, fn, *args):
+        a, b = fn(*[x[0] for x in args]), fn(*[x[1] for x in args])
+        for x, y in zip(a if isinstance(a, tuple) else (a,), b if isinstance(b, tuple) else (b,)):
+            assert torch.equal(x, y), name
+
+    same("cons2prim", lambda U: F.cons2prim(U, GAMMA), (Uu, Ua))
+    same("prim2cons", lambda V: F.prim2cons(V, GAMMA), (Vu, Va))
+    same("v_mag2", F.velocity_magnitude2, (Uu, Ua))
+    same("flux", lambda U: F.flux(U, GAMMA), (Uu, Ua))
+    same("riemann_invariants", lambda U: F.riemann_invariants(U, GAMMA), (Uu, Ua))
+    same("fused", lambda U: F.euler_fused(U, GAMMA), (Uu, Ua))
+    same("adjoint", lambda U, Fb: F.flux_adjoint(U, Fb, GAMMA), (Uu, Ua), (Fbu, Fba))
+    same("roe_average", lambda U, UR: F.roe_average(U, UR, GAMMA), (Uu, Ua), (URu, URa))
+    same("char_apply", lambda U, X: F.char_apply(U, X, dim - 1, 1, GAMMA), (Uu, Ua), (Xu, Xa))
+    same("eigenvectors", lambda U: F.eigenvectors(U, GAMMA), (Uu, Ua))
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("dim", DIMS)
 def test_in_place_transforms(dim, dt):
     n = 2049
     Uo, Ug = states(dim, n, 31, dt)
