@@ -5,6 +5,9 @@
  * building blocks of the method; they bound them: every building block is a
  * pure streaming pass, so these rates are its practical ceiling.
  *
+ * Accesses are 16 bytes per lane; stores are streaming stores with the nt
+ * and sc1 cache-policy bits, as in the fused kernel.
+ *
  * Pointers are device pointers, 16-byte aligned; `bytes` is a multiple of
  * 16.  Calls enqueue one kernel on `stream` (hipStream_t as void*, NULL for
  * the default stream) and return at once.  Return values are fdbb_status
@@ -36,7 +39,8 @@ int fdbb_probe_read(const void *src, int64_t bytes, uint64_t *sink, int grid, vo
  * Jacobian blocks A, 3 x n blocks of 25 doubles; all with ld = n), with its
  * tiling (128 threads per workgroup, 4 points per thread, each wave storing
  * its 256 points' F and R chunk by chunk, then its blocks one direction at a
- * time).  Writes 776 bytes per point.  n must be a positive multiple of 512
+ * time), and its store flavour (nt + sc1).  Writes 776 bytes per point.
+ * n must be a positive multiple of 512
  * (FDBB_EINVAL otherwise); the arrays are FP64 and 16-byte aligned. */
 int fdbb_probe_fused_stores(double *F, double *R, double *A, int64_t n, void *stream);
 
