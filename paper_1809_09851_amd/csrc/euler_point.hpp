@@ -230,11 +230,83 @@ __device__ __forceinline__ Waves make_waves(const Gas &g, const State<D> &s)
 // 1e-14 for |y log x| < 40).  x <= 0 gives NaN or the limit at 0, as pow.
 __device__ __forceinline__ double pos_pow(double x, double y) { return exp(y * log(x)); }
 
+// The same power with shorter series, for outputs stored in FP32, where
+// the library's exp and log make the entropy-carrying transforms bound by
+// the FP64 instruction rate rather than by HBM.  Still FP64 throughout:
+// relative error below 5e-14 (x = e^-12..e^12, |y| <= 3), far under the
+// 6e-8 rounding of the FP32 store.  Zero, negative and non-finite
+// arguments give the IEEE results of log and exp (selected, not branched,
+// so the library code and its registers stay out of the kernel); results
+// beyond the range of doubles saturate to inf or 0, subnormal ones are
+// formed by the final scaling.
+
+// log x: for finite x > 0, x = m 2^e with m in [sqrt(1/2), sqrt(2)), and
+// log m = 2 atanh(t) with t = (m - 1)/(m + 1), |t| < 0.1716, summed as the
+// odd series 2 (t + t^3/3 + ... + t^15/15); ln 2 in two parts.
+__device__ __forceinline__ double log_short(double x)
+{
+    const bool ok = x > 0.0 && x < INFINITY;
+    int e;
+    double m = frexp(ok ? x : 1.0, &e);
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        --e;
+    }
+    const double t = (m - 1.0) / (m + 1.0);
+    const double t2 = t * t;
+    double p = 1.0 / 15.0;
+    p = fma(p, t2, 1.0 / 13.0);
+    p = fma(p, t2, 1.0 / 11.0);
+    p = fma(p, t2, 1.0 / 9.0);
+    p = fma(p, t2, 1.0 / 7.0);
+    p = fma(p, t2, 1.0 / 5.0);
+    p = fma(p, t2, 1.0 / 3.0);
+    p = fma(p, t2, 1.0);
+    const double ln2_hi = 6.93147180369123816490e-01, ln2_lo = 1.90821492927058770002e-10;
+    const double r = fma((double)e, ln2_hi, fma((double)e, ln2_lo, 2.0 * t * p));
+    // log 0 = -inf, log inf = inf, NaN below zero and for NaN
+    return ok ? r : (x == 0.0 ? -INFINITY : (x == INFINITY ? INFINITY : NAN));
+}
+
+// e^z: z = k ln 2 + r with |r| <= ln 2 / 2 (ln 2 in two parts), e^r by
+// its Taylor series to degree 12, scaled by 2^k.
+__device__ __forceinline__ double exp_short(double z)
+{
+    // beyond +-800 the scaling by 2^k saturates to inf or 0, as exp does
+    const double zc = fmin(fmax(z, -800.0), 800.0);
+    const double k = rint(zc * 1.44269504088896340736);
+    const double ln2_hi = 6.93147180369123816490e-01, ln2_lo = 1.90821492927058770002e-10;
+    const double r = fma(-k, ln2_lo, fma(-k, ln2_hi, zc));
+    double p = 1.0 / 479001600.0;
+    p = fma(p, r, 1.0 / 39916800.0);
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    const double v = ldexp(p, (int)k);
+    return z != z ? z : v;
+}
+
+// x^y for x > 0: with the short series when SHORT (FP32 storage).
+template <bool SHORT>
+__device__ __forceinline__ double pos_pow_t(double x, double y)
+{
+    if constexpr (SHORT) return exp_short(y * log_short(x));
+    else return pos_pow(x, y);
+}
+
 // Entropy s = p / rho^gamma.
-template <int D>
+template <int D, bool SHORT = false>
 __device__ __forceinline__ double entropy(const Gas &g, const State<D> &s)
 {
-    return s.p * pos_pow(s.rho, -g.gamma);
+    return s.p * pos_pow_t<SHORT>(s.rho, -g.gamma);
 }
 
 // Adjoint contribution of direction d: ubar += A_d^T fb, where fb = (a,

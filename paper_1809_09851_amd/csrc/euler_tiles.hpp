@@ -519,7 +519,7 @@ __device__ __forceinline__ void store_riemann(const Args &a, const Lane<T, P, NT
     }
     double en[W];
 #pragma unroll
-    for (int j = 0; j < W; ++j) en[j] = entropy<D>(a.gas, s[j]);
+    for (int j = 0; j < W; ++j) en[j] = entropy<D, sizeof(T) == 4>(a.gas, s[j]);
     L.store(R, ldR, 2 * D, c, en);
 }
 
@@ -601,7 +601,7 @@ __device__ __forceinline__ void tile_cons2char(const Args &a, int64_t tile0)
             for (int k = 1; k < D; ++k)
                 if (k == dir) vd = s.v[k];
             out[0][j] = vd - t;
-            out[1][j] = entropy<D>(a.gas, s);
+            out[1][j] = entropy<D, sizeof(T) == 4>(a.gas, s);
             out[K - 1][j] = vd + t;
             // tangential components: slot 2 + (k < dir ? k : k - 1) for k != dir
 #pragma unroll
@@ -640,7 +640,7 @@ __device__ __forceinline__ void tile_char2cons(const Args &a, int64_t tile0)
             const double cs = g.quarter_g1 * (wp - wm);
             const double c2 = cs * cs;
             // rho = (c^2 / (gamma s))^(1/(gamma-1)),  p = rho c^2 / gamma
-            const double rho = pos_pow(c2 * g.inv_gamma / s, g.inv_g1);
+            const double rho = pos_pow_t<sizeof(T) == 4>(c2 * g.inv_gamma / s, g.inv_g1);
             const double p = rho * c2 * g.inv_gamma;
             double vp[K];
             vp[0] = rho;
