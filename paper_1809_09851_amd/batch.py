@@ -31,7 +31,7 @@ def _set(t, slot, tensor, fields=None, dim=None, blocks=False):
     if blocks:
         ptr, ld = F._blocks(tensor, dim)
     elif fields is None:
-        ptr, ld = tensor.data_ptr(), 0
+        ptr, ld = F._dptr(tensor, slot), 0
     else:
         ptr, ld = F._fields(tensor, fields, slot)
     setattr(t, slot, ptr)

@@ -69,6 +69,19 @@ __global__ __launch_bounds__(128) void k_fused_stores(double *__restrict__ F, do
     }
 }
 
+// x^y = exp(y log x) for each element, by the library's exp and log
+// (SHORT false, the FP64-storage kernels) or by the short series of the
+// FP32-storage kernels (SHORT true): the same device functions the building
+// blocks call.  One element per thread, grid-stride; regular stores.
+template <bool SHORT>
+__global__ __launch_bounds__(256) void k_pow(const double *__restrict__ x, const double *__restrict__ y,
+                                            double *__restrict__ out, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
+        out[i] = fdbb::pos_pow_t<SHORT>(x[i], y[i]);
+}
+
 int grid_for(int grid)
 {
     if (grid > 0) return grid;
@@ -79,6 +92,8 @@ int grid_for(int grid)
 }
 
 bool aligned(const void *p) { return p && ((uintptr_t)p % 16) == 0; }
+
+bool aligned8(const void *p) { return p && ((uintptr_t)p % 8) == 0; }
 
 }  // namespace
 
@@ -121,6 +136,21 @@ int fdbb_probe_fused_stores(double *F, double *R, double *A, int64_t n, void *st
 {
     if (!aligned(F) || !aligned(R) || !aligned(A) || n <= 0 || n % 512) return FDBB_EINVAL;
     hipLaunchKernelGGL(k_fused_stores, dim3((unsigned)(n / 512)), dim3(128), 0, (hipStream_t)stream, F, R, A, n);
+    return hipGetLastError() == hipSuccess ? FDBB_OK : FDBB_EHIP;
+}
+
+int fdbb_probe_pow(const double *x, const double *y, double *out, int64_t n, int short_series, void *stream)
+{
+    if (!aligned8(x) || !aligned8(y) || !aligned8(out) || n < 0) return FDBB_EINVAL;
+    if (n == 0) return FDBB_OK;
+    const int cap = grid_for(0);
+    if (cap <= 0) return FDBB_EHIP;
+    const int64_t want = (n + 255) / 256;
+    const unsigned g = (unsigned)(want < cap ? want : cap);
+    if (short_series)
+        hipLaunchKernelGGL(k_pow<true>, dim3(g), dim3(256), 0, (hipStream_t)stream, x, y, out, n);
+    else
+        hipLaunchKernelGGL(k_pow<false>, dim3(g), dim3(256), 0, (hipStream_t)stream, x, y, out, n);
     return hipGetLastError() == hipSuccess ? FDBB_OK : FDBB_EHIP;
 }
 

@@ -121,6 +121,7 @@ def library():
         lib.fdbb_probe_write.argtypes = [_p, _i64, ctypes.c_uint64, _i, _p]
         lib.fdbb_probe_read.argtypes = [_p, _i64, _p, _i, _p]
         lib.fdbb_probe_fused_stores.argtypes = [_p, _p, _p, _i64, _p]
+        lib.fdbb_probe_pow.argtypes = [_p, _p, _p, _i64, _i, _p]
         _lib = lib
         if os.environ.get("FDBB_NO_TUNED_TABLE") != "1":
             from . import tune
@@ -152,10 +153,18 @@ def _stream(stream):
     return int(stream)
 
 
+def _dptr(t: torch.Tensor, name: str = "tensor") -> int:
+    """Data pointer of a device tensor; a host tensor is refused here, since
+    every entry point hands its pointers to kernels."""
+    if not t.is_cuda:
+        raise ValueError(f"{name}: expected a tensor in device memory, got one on {t.device}")
+    return t.data_ptr()
+
+
 def _ptr(t):
     if t is None:
         return None
-    return t.data_ptr()
+    return _dptr(t)
 
 
 def _fields(t: torch.Tensor, fields: int, name: str):
@@ -165,7 +174,7 @@ def _fields(t: torch.Tensor, fields: int, name: str):
     if t.shape[1] > 1 and t.stride(1) != 1:
         raise ValueError(f"{name}: points must be contiguous (stride 1)")
     ld = t.stride(0) if fields > 1 else max(t.shape[1], 1)
-    return t.data_ptr(), ld
+    return _dptr(t, name), ld
 
 
 def _blocks(A: torch.Tensor, dim: int, name: str = "A"):
@@ -174,7 +183,7 @@ def _blocks(A: torch.Tensor, dim: int, name: str = "A"):
         raise ValueError(f"{name}: expected shape ({dim}, n, {K}, {K}), got {tuple(A.shape)}")
     if A.stride(3) != 1 or A.stride(2) != K or A.stride(1) != K * K or A.stride(0) % (K * K):
         raise ValueError(f"{name}: blocks must be point-major row-major")
-    return A.data_ptr(), A.stride(0) // (K * K)
+    return _dptr(A, name), A.stride(0) // (K * K)
 
 
 def padded_ld(n: int) -> int:
@@ -228,7 +237,7 @@ def fdbb_velocity_magnitude2(dim, U, y, n=None, stream=None):
     if U.shape[1] > 1 and U.stride(1) != 1:
         raise ValueError("U: points must be contiguous (stride 1)")
     n = U.shape[1] if n is None else n
-    check(library().fdbb_velocity_magnitude2(dim, dtype_code(U.dtype), U.data_ptr(), U.stride(0), y.data_ptr(),
+    check(library().fdbb_velocity_magnitude2(dim, dtype_code(U.dtype), _dptr(U, "U"), U.stride(0), _dptr(y, "y"),
                                              n, _stream(stream)))
 
 
@@ -331,7 +340,7 @@ def fdbb_eos_pvt(dim, eos, params, U, p=None, c=None, T=None, n=None, stream=Non
     prm = (ctypes.c_double * 3)(*(list(params) + [0.0] * (3 - len(params))))
     u, ldu = _fields(U, dim + 2, "U")
     n = U.shape[1] if n is None else n
-    ptr = [t.data_ptr() if t is not None else None for t in (p, c, T)]
+    ptr = [_ptr(t) for t in (p, c, T)]
     check(library().fdbb_eos_pvt(dim, eos, ctypes.cast(prm, _p), dtype_code(U.dtype), u, ldu, *ptr, n,
                                  _stream(stream)))
 
@@ -459,24 +468,38 @@ def flux_adjoint(U, Fbar, gamma=1.4, direction=-1, stream=None):
 # ------------------------------------------------------------ streaming probes
 def probe_copy(src: torch.Tensor, dst: torch.Tensor, grid: int = 0, stream=None):
     nbytes = min(src.numel() * src.element_size(), dst.numel() * dst.element_size())
-    check(library().fdbb_probe_copy(src.data_ptr(), dst.data_ptr(), nbytes // 16 * 16, grid,
+    check(library().fdbb_probe_copy(_dptr(src), _dptr(dst), nbytes // 16 * 16, grid,
                                     _stream(stream)))
 
 
 def probe_write(dst: torch.Tensor, pattern: int = 0x3FF0000000000000, grid: int = 0, stream=None):
     nbytes = dst.numel() * dst.element_size()
-    check(library().fdbb_probe_write(dst.data_ptr(), nbytes // 16 * 16, pattern, grid, _stream(stream)))
+    check(library().fdbb_probe_write(_dptr(dst), nbytes // 16 * 16, pattern, grid, _stream(stream)))
 
 
 def probe_fused_stores(F_: torch.Tensor, R: torch.Tensor, A: torch.Tensor, n: int, stream=None):
     """The fused 3D pass's stores alone (constant values, same layout and
     order): F (15, n), R (7, n), A (3, n, 5, 5), FP64, n a multiple of 512."""
-    check(library().fdbb_probe_fused_stores(F_.data_ptr(), R.data_ptr(), A.data_ptr(), n, _stream(stream)))
+    check(library().fdbb_probe_fused_stores(_dptr(F_), _dptr(R), _dptr(A), n, _stream(stream)))
+
+
+def probe_pow(x: torch.Tensor, y: torch.Tensor, short_series: bool, stream=None) -> torch.Tensor:
+    """x ** y elementwise on the device, by the power the building blocks
+    use: the library's exp and log, or the short series of the FP32-storage
+    kernels.  x and y: contiguous FP64 device tensors of one shape."""
+    if x.dtype != torch.float64 or y.dtype != torch.float64 or x.shape != y.shape:
+        raise ValueError("probe_pow takes two FP64 tensors of one shape")
+    if not (x.is_contiguous() and y.is_contiguous()):
+        raise ValueError("probe_pow takes contiguous tensors")
+    out = torch.empty_like(x)
+    check(library().fdbb_probe_pow(_dptr(x), _dptr(y), _dptr(out), x.numel(),
+                                   1 if short_series else 0, _stream(stream)))
+    return out
 
 
 def probe_read(src: torch.Tensor, sink: torch.Tensor, grid: int = 0, stream=None):
     nbytes = src.numel() * src.element_size()
-    check(library().fdbb_probe_read(src.data_ptr(), nbytes // 16 * 16, sink.data_ptr(), grid,
+    check(library().fdbb_probe_read(_dptr(src), nbytes // 16 * 16, _dptr(sink), grid,
                                     _stream(stream)))
 
 

@@ -236,6 +236,27 @@ def test_fused_store_probe_checks():
     assert lib.fdbb_probe_fused_stores(A0, B0, A0 + (1 << 30), 0, None) == F.EINVAL
 
 
+def test_pow_probe_checks():
+    lib = F.library()
+    big = A0 + (1 << 30)
+    assert lib.fdbb_probe_pow(A0, B0, big, -1, 1, None) == F.EINVAL
+    assert lib.fdbb_probe_pow(A0 + 4, B0, big, 16, 1, None) == F.EINVAL  # misaligned
+    assert lib.fdbb_probe_pow(None, B0, big, 16, 0, None) == F.EINVAL
+    assert lib.fdbb_probe_pow(A0, B0, None, 16, 0, None) == F.EINVAL
+    assert lib.fdbb_probe_pow(A0, B0, big, 0, 1, None) == F.OK  # nothing to do, no launch
+
+
+def test_binding_refuses_host_tensors():
+    """Host tensors are refused before any pointer reaches the library."""
+    import torch
+    U = torch.ones(5, 64, dtype=torch.float64)
+    V = torch.empty_like(U)
+    with pytest.raises(ValueError, match="device memory"):
+        F.fdbb_cons2prim(3, 1.4, U, V)
+    with pytest.raises(ValueError, match="device memory"):
+        F.probe_pow(U[0].contiguous(), U[1].contiguous(), True)
+
+
 def test_headers_are_plain_c_and_cpp(tmp_path):
     """The public headers compile as strict C99 and as C++11, so that a C
     caller needs nothing but the headers and libfdbb.so."""
