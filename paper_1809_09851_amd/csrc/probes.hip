@@ -1,7 +1,8 @@
-// Streaming probes (declared in include/fdbb_probe.h): grid-stride loops of
-// 16-byte accesses, 256 threads per workgroup.  grid <= 0 launches 8
-// workgroups per compute unit.  Stores are the streaming stores of the
-// fused kernel (nt + sc1, fdbb::put<kStoreNTSc1>).
+// Probes (declared in include/fdbb_probe.h).  The streaming probes are
+// grid-stride loops of 16-byte accesses, 256 threads per workgroup; grid <= 0
+// launches 8 workgroups per compute unit; their stores are the streaming
+// stores of the fused kernel (nt + sc1, fdbb::put<kStoreNTSc1>).  The power
+// probe evaluates the building blocks' shared power elementwise.
 #include "../../include/fdbb.h"
 #include "../../include/fdbb_probe.h"
 
