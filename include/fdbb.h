@@ -91,7 +91,8 @@ typedef enum {
     FDBB_OP_ROE_AVERAGE = 13,
     FDBB_OP_EOS_PVT = 14,
     FDBB_OP_VISCOUS_FLUX = 15,
-    FDBB_NUM_OPS = 16
+    FDBB_OP_FLUX_DIR = 16,
+    FDBB_NUM_OPS = 17
 } fdbb_op;
 
 /* Conservative -> primitive (Sec. 2.2, "Variables", conversion figure):
@@ -123,6 +124,13 @@ int fdbb_eos(int dim, double gamma, int dtype, const void *U, int64_t ldU,
  * F has K * D fields, field r * D + d = component r of F_d. */
 int fdbb_flux(int dim, double gamma, int dtype, const void *U, int64_t ldU,
               void *F, int64_t ldF, int64_t n, void *stream);
+
+/* The flux of one direction alone (Sec. 2.2, "Inviscid Fluxes": column `dir`
+ * of the K x D flux block): F_dir = (m_dir, m v_dir + e_dir p, v_dir (E + p)).
+ * Fd has K fields, field r = component r of F_dir; reads K fields and writes
+ * K, where fdbb_flux writes K * D.  0 <= dir < dim, else FDBB_EINVAL. */
+int fdbb_flux_direction(int dim, int dir, double gamma, int dtype, const void *U, int64_t ldU,
+                        void *Fd, int64_t ldFd, int64_t n, void *stream);
 
 /* Flux Jacobians A_d = dF_d / dU for d = 0..D-1 (Fig. 1, "flux-Jacobians";
  * the paper leaves them unfinished, Sec. 2.2, "Inviscid Fluxes"; these are
@@ -256,13 +264,13 @@ int fdbb_kernel_info(int op, int dim, int dtype, int ppt, int nontemporal, int *
  * names one operation on one field-set group; its fields mean what the
  * matching single-call entry point's arguments mean:
  *   in0  = U (V for prim2cons, W for char2cons), in1 = Fbar (adjoint only),
- *   out0 = V / U / p / F / A / R / W / Ubar / y (v_mag2), out1 = c (eos) or A (fused),
+ *   out0 = V / U / p / F / F_dir / A / R / W / Ubar / y (v_mag2), out1 = c (eos) or A (fused),
  *   out2 = R (fused).  Unused pointers are NULL. */
 typedef struct {
     int32_t op;     /* fdbb_op */
     int32_t dim;
     int32_t dtype;  /* fdbb_dtype */
-    int32_t dir;    /* direction for cons2char/char2cons/adjoint, else 0 */
+    int32_t dir;    /* direction for cons2char/char2cons/adjoint/flux_dir, else 0 */
     double gamma;
     int64_t n;
     const void *in0;

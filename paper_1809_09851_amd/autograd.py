@@ -22,14 +22,11 @@ class EulerFlux(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, U, gamma=1.4, direction=None):
-        dim = U.shape[0] - 2
-        Fu = F.flux(U, gamma)
+        # one direction evaluates and stores only F_direction (K fields)
         ctx.save_for_backward(U)
         ctx.gamma = gamma
         ctx.direction = direction
-        if direction is None:
-            return Fu
-        return Fu[direction::dim]
+        return F.flux(U, gamma, direction=direction)
 
     @staticmethod
     def backward(ctx, gF):

@@ -17,6 +17,7 @@ enum : int32_t {
     kFlagInPlace = 1,  // K -> K transform with output == input: skip the rho store
     kFlagVector = 2,   // every base pointer and row stride allows 16-byte access
     kFlagRight = 4,    // characteristic product with R (else with L)
+    kFlagOneDir = 8,   // flux of direction Args::dir only, as K fields
 };
 
 // One operation on one field-set group (the device image of fdbb_task).
@@ -497,6 +498,26 @@ __device__ __forceinline__ void store_flux(const Lane<T, P, NT> &L, const State<
     }
 }
 
+// The K components of F_dir alone (field r = component r), of W points.
+// dir is uniform over the launch, so the test below does not diverge.
+template <int D, typename T, int P, int NT>
+__device__ __forceinline__ void store_flux_dir(const Lane<T, P, NT> &L, const State<D> *s, int c, int dir,
+                                               void *F, int64_t ldF)
+{
+    constexpr int W = Lane<T, P, NT>::W;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        if (d != dir) continue;
+#pragma unroll
+        for (int r = 0; r < D + 2; ++r) {
+            double f[W];
+#pragma unroll
+            for (int j = 0; j < W; ++j) f[j] = flux_entry<D>(s[j], r, d);
+            L.store(F, ldF, r, c, f);
+        }
+    }
+}
+
 // Riemann invariants of every direction and the entropy, of W points.
 template <int D, typename T, int P, int NT>
 __device__ __forceinline__ void store_riemann(const Args &a, const Lane<T, P, NT> &L, const State<D> *s, int c,
@@ -544,7 +565,8 @@ __device__ __forceinline__ void tile_flux(const Args &a, int64_t tile0)
             for (int k = 0; k < K; ++k) uj[k] = u[c][k][j];
             s[j] = make_state<D>(a.gas, uj);
         }
-        store_flux<D, T, P, NT>(L, s, c, a.out0, a.ld_out0);
+        if (a.flags & kFlagOneDir) store_flux_dir<D, T, P, NT>(L, s, c, a.dir, a.out0, a.ld_out0);
+        else store_flux<D, T, P, NT>(L, s, c, a.out0, a.ld_out0);
     }
 }
 

@@ -36,30 +36,36 @@ size_t elem_size(int dtype) { return dtype == FDBB_F64 ? 8 : 4; }
 // ------------------------------------------------------------ device facts
 
 struct DeviceInfo {
+    int id = 0;
     int cus = 0;
     size_t lds_max = 0;
 };
 
-std::mutex g_dev_mutex;
-DeviceInfo g_dev[64];
+// Per-device facts, read once and then served without a lock: the first
+// callers on a device may query concurrently, and all store the same values.
+constexpr int kMaxDevices = 64;
+std::atomic<int> g_dev_cus[kMaxDevices];
+std::atomic<int64_t> g_dev_lds[kMaxDevices];
 
 int device_info(DeviceInfo *out)
 {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
-    if (dev < 0 || dev >= 64) return fail(FDBB_EHIP, "device index out of range");
-    std::lock_guard<std::mutex> lock(g_dev_mutex);
-    if (g_dev[dev].cus == 0) {
-        int cus = 0, lds = 0;
+    if (dev < 0 || dev >= kMaxDevices) return fail(FDBB_EHIP, "device index out of range");
+    int cus = g_dev_cus[dev].load(std::memory_order_acquire);
+    if (cus == 0) {
+        int lds = 0;
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return fail_hip(e, "hipDeviceGetAttribute");
         e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
         if (e != hipSuccess) return fail_hip(e, "hipDeviceGetAttribute");
-        g_dev[dev].cus = cus;
-        g_dev[dev].lds_max = (size_t)lds;
+        g_dev_lds[dev].store(lds, std::memory_order_relaxed);
+        g_dev_cus[dev].store(cus, std::memory_order_release);
     }
-    *out = g_dev[dev];
+    out->id = dev;
+    out->cus = cus;
+    out->lds_max = (size_t)g_dev_lds[dev].load(std::memory_order_relaxed);
     return FDBB_OK;
 }
 
@@ -178,7 +184,8 @@ Gas make_gas(double gamma)
 struct Call {
     int op = 0, dim = 0, dtype = 0;
     Args a{};
-    std::vector<Range> ranges;  // for alias checks
+    Range ranges[8];            // field sets of the call, for alias checks
+    int nranges = 0;
     bool inplace_ok = false;    // K -> K transform
     size_t unit_out0 = 1;       // elements per point of out0 (K*K for blocks)
     size_t unit_out1 = 1;       // elements per point of out1 (K*K for blocks)
@@ -197,15 +204,18 @@ int add_fields(Call &c, const void *base, int64_t ld, int64_t fields, int64_t un
     if (fields > 1 && ld < n) return fail(FDBB_EINVAL, std::string("ld of ") + name + " must be >= n");
     if ((uintptr_t)base % es != 0)
         return fail(FDBB_EALIGN, std::string(name) + " is not aligned to its element size");
-    if (n > 0) c.ranges.push_back(field_range(base, fields > 1 ? ld : 0, fields, n, unit, es, input));
+    if (n > 0) {
+        if (c.nranges >= 8) return fail(FDBB_EINVAL, "too many field sets in one call");
+        c.ranges[c.nranges++] = field_range(base, fields > 1 ? ld : 0, fields, n, unit, es, input);
+    }
     return FDBB_OK;
 }
 
 int check_alias(const Call &c)
 {
-    const auto &R = c.ranges;
-    for (size_t i = 0; i < R.size(); ++i)
-        for (size_t j = i + 1; j < R.size(); ++j) {
+    const Range *R = c.ranges;
+    for (int i = 0; i < c.nranges; ++i)
+        for (int j = i + 1; j < c.nranges; ++j) {
             if (R[i].input && R[j].input) continue;
             if (!overlap(R[i], R[j])) continue;
             const bool exact = R[i].base == R[j].base && R[i].ld == R[j].ld && R[i].input != R[j].input;
@@ -237,7 +247,8 @@ int family_of(int op)
     case FDBB_OP_CONS2PRIM: return kFamCons2Prim;
     case FDBB_OP_PRIM2CONS: return kFamPrim2Cons;
     case FDBB_OP_EOS: return kFamEos;
-    case FDBB_OP_FLUX: return kFamFlux;
+    case FDBB_OP_FLUX:
+    case FDBB_OP_FLUX_DIR: return kFamFlux;
     case FDBB_OP_RIEMANN: return kFamRiemann;
     case FDBB_OP_CONS2CHAR: return kFamCons2Char;
     case FDBB_OP_CHAR2CONS: return kFamChar2Cons;
@@ -287,16 +298,33 @@ size_t lds_bytes(int op, int dim, int dtype, int block, int ppt)
     return (size_t)block * ppt * K * K * elem_size(dtype);
 }
 
-std::mutex g_attr_mutex;
+// Kernels whose dynamic-LDS limit has been raised on a device, as an
+// open-addressed set of (kernel address | device << 56) keys.  The limit is
+// raised once, to the device maximum, the first time a kernel needs more
+// than the default 64 KB; later launches only look the key up (no lock, no
+// runtime call).  Two threads may both raise it for the same kernel the
+// first time; the call is idempotent.
+constexpr int kAttrSlots = 4096;
+std::atomic<uintptr_t> g_attr_done[kAttrSlots];
 
 int set_lds_attr(const void *fn, size_t lds, const DeviceInfo &dev)
 {
     if (lds <= 65536) return FDBB_OK;
     if (lds > dev.lds_max) return fail(FDBB_EINVAL, "launch configuration needs more LDS than a workgroup may use");
-    std::lock_guard<std::mutex> lock(g_attr_mutex);
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return fail_hip(e, "hipFuncSetAttribute");
-    return FDBB_OK;
+    const uintptr_t key = (uintptr_t)fn | ((uintptr_t)(dev.id + 1) << 56);
+    size_t h = (size_t)((key >> 4) * 0x9E3779B97F4A7C15ull) % kAttrSlots;
+    for (int probe = 0; probe < kAttrSlots; ++probe, h = (h + 1) % kAttrSlots) {
+        uintptr_t v = g_attr_done[h].load(std::memory_order_acquire);
+        if (v == key) return FDBB_OK;
+        if (v != 0) continue;
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dev.lds_max);
+        if (e != hipSuccess) return fail_hip(e, "hipFuncSetAttribute");
+        uintptr_t expected = 0;
+        if (g_attr_done[h].compare_exchange_strong(expected, key, std::memory_order_acq_rel)) return FDBB_OK;
+        if (expected == key) return FDBB_OK;
+        // another kernel took this slot meanwhile: keep probing
+    }
+    return FDBB_OK;  // table full (more kernels than exist): the limit is raised anyway
 }
 
 int launch(Call &c, void *stream)
@@ -382,6 +410,14 @@ int build_call(Call &c, const fdbb_task &t, int mode = 0)
         a.in0 = t.in0, a.ld_in0 = t.ld_in0, a.out0 = t.out0, a.ld_out0 = t.ld_out0;
         if ((rc = add_fields(c, t.in0, t.ld_in0, K, 1, true, true, "U"))) return rc;
         if ((rc = add_fields(c, t.out0, t.ld_out0, (int64_t)K * D, 1, false, true, "F"))) return rc;
+        break;
+    case FDBB_OP_FLUX_DIR:
+        if (t.dir < 0 || t.dir >= D) return fail(FDBB_EINVAL, "dir out of range");
+        a.dir = t.dir;
+        a.flags |= kFlagOneDir;
+        a.in0 = t.in0, a.ld_in0 = t.ld_in0, a.out0 = t.out0, a.ld_out0 = t.ld_out0;
+        if ((rc = add_fields(c, t.in0, t.ld_in0, K, 1, true, true, "U"))) return rc;
+        if ((rc = add_fields(c, t.out0, t.ld_out0, K, 1, false, true, "F_dir"))) return rc;
         break;
     case FDBB_OP_EIGENVECTORS:
         if (!t.out0 && !t.out1 && t.n > 0) return fail(FDBB_EINVAL, "L and R must not both be NULL");
@@ -539,6 +575,14 @@ int fdbb_flux(int dim, double gamma, int dtype, const void *U, int64_t ldU, void
 {
     fdbb_task t = make_task(FDBB_OP_FLUX, dim, 0, gamma, dtype, n);
     t.in0 = U, t.ld_in0 = ldU, t.out0 = F, t.ld_out0 = ldF;
+    return run(t, stream);
+}
+
+int fdbb_flux_direction(int dim, int dir, double gamma, int dtype, const void *U, int64_t ldU, void *Fd,
+                        int64_t ldFd, int64_t n, void *stream)
+{
+    fdbb_task t = make_task(FDBB_OP_FLUX_DIR, dim, dir, gamma, dtype, n);
+    t.in0 = U, t.ld_in0 = ldU, t.out0 = Fd, t.ld_out0 = ldFd;
     return run(t, stream);
 }
 
@@ -743,11 +787,20 @@ const char *fdbb_status_string(int status)
 
 const char *fdbb_last_error(void) { return g_last_error.c_str(); }
 
-int fdbb_version(void) { return 200; }
+int fdbb_version(void) { return 300; }
 
 }  // extern "C"
 
 // ================================================================ batches
+
+// Layout of a task table, on the device and in its host staging copy:
+// [header: ntasks, ntiles (int64)][tile prefix sums, cap + 1 int64][pad to
+// 64 B][cap TaskDev].
+static size_t table_task_offset(int cap) { return ((2 + (size_t)cap + 1) * sizeof(int64_t) + 63) & ~(size_t)63; }
+static size_t table_bytes(int cap) { return table_task_offset(cap) + (size_t)cap * sizeof(TaskDev); }
+static int64_t *table_header(unsigned char *base) { return reinterpret_cast<int64_t *>(base); }
+static int64_t *table_prefix(unsigned char *base) { return reinterpret_cast<int64_t *>(base) + 2; }
+static TaskDev *table_tasks(unsigned char *base, int cap) { return reinterpret_cast<TaskDev *>(base + table_task_offset(cap)); }
 
 struct fdbb_batch_plan {
     int device = 0;
@@ -760,30 +813,81 @@ struct fdbb_batch_plan {
     int64_t points = 0;
     int64_t tiles = 0;
     const void *kernel = nullptr;
-    unsigned char *dev = nullptr;   // [header 2 x int64][prefix cap+1][tasks cap]
+    unsigned char *dev = nullptr;   // task table (layout above), capacity `capacity`
     unsigned char *host = nullptr;  // pinned staging copy of the same layout
     size_t bytes = 0;
     hipEvent_t uploaded = nullptr;  // the last upload has left the staging copy
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 
-    int64_t *header(unsigned char *base) const { return reinterpret_cast<int64_t *>(base); }
-    int64_t *prefix(unsigned char *base) const { return reinterpret_cast<int64_t *>(base) + 2; }
-    TaskDev *tasks(unsigned char *base) const
-    {
-        size_t off = (2 + (size_t)capacity + 1) * sizeof(int64_t);
-        off = (off + 63) & ~(size_t)63;
-        return reinterpret_cast<TaskDev *>(base + off);
-    }
+    int64_t *header(unsigned char *base) const { return table_header(base); }
+    int64_t *prefix(unsigned char *base) const { return table_prefix(base); }
+    TaskDev *tasks(unsigned char *base) const { return table_tasks(base, capacity); }
 };
 
 namespace {
 
-size_t plan_bytes(int capacity)
+// What filling a task table found.
+struct TableInfo {
+    size_t lds = 0;      // dynamic LDS the tasks' Jacobian staging needs
+    int64_t tiles = 0;
+    int64_t points = 0;
+};
+
+// Validate `tasks` (each as its single-call entry point would, then every
+// pair of tasks for overlapping outputs) and write the table for tiles of
+// block * ppt points into `host` (layout above, capacity `cap`).  `all`
+// must have room for 8 * ntasks ranges.  Uses no heap memory of its own.
+int fill_table(const fdbb_task *tasks, int ntasks, int cap, int block, int ppt, unsigned char *host, Range *all,
+               TableInfo *info)
 {
-    size_t off = (2 + (size_t)capacity + 1) * sizeof(int64_t);
-    off = (off + 63) & ~(size_t)63;
-    return off + (size_t)capacity * sizeof(TaskDev);
+    if (ntasks > 0 && !tasks) return fail(FDBB_EINVAL, "tasks must not be NULL");
+    int64_t *hdr = table_header(host);
+    int64_t *pre = table_prefix(host);
+    TaskDev *td = table_tasks(host, cap);
+    const int64_t tile_pts = (int64_t)block * ppt;
+    size_t nall = 0;
+    TableInfo r;
+    for (int b = 0; b < ntasks; ++b) {
+        if (!batchable(tasks[b].op))
+            return fail(FDBB_EINVAL, "task " + std::to_string(b) + ": op not available in batches");
+        Call c;
+        int rc = build_call(c, tasks[b]);
+        if (rc) return fail(rc, "task " + std::to_string(b) + ": " + g_last_error);
+        rc = check_alias(c);
+        if (rc) return fail(rc, "task " + std::to_string(b) + ": " + g_last_error);
+        if (vector_ok(c)) c.a.flags |= kFlagVector;
+        const bool jac = tasks[b].op == FDBB_OP_FLUX_JACOBIAN || (tasks[b].op == FDBB_OP_FUSED && tasks[b].out1);
+        if (jac) r.lds = std::max(r.lds, lds_bytes(tasks[b].op, tasks[b].dim, tasks[b].dtype, block, ppt));
+        for (int k = 0; k < c.nranges; ++k) {
+            all[nall] = c.ranges[k];
+            all[nall].task = b;
+            ++nall;
+        }
+        pre[b] = r.tiles;
+        r.tiles += (tasks[b].n + tile_pts - 1) / tile_pts;
+        r.points += tasks[b].n;
+        td[b].a = c.a;
+        td[b].op = tasks[b].op;
+        td[b].dim = tasks[b].dim;
+        td[b].dtype = tasks[b].dtype;
+        td[b].pad = 0;
+    }
+    // Across tasks: no output may overlap another task's input or output.
+    std::sort(all, all + nall, [](const Range &x, const Range &y) { return x.lo < y.lo; });
+    for (size_t i = 0; i < nall; ++i) {
+        for (size_t j = i + 1; j < nall && all[j].lo < all[i].hi; ++j) {
+            if (all[i].task == all[j].task) continue;
+            if (all[i].input && all[j].input) continue;
+            return fail(FDBB_EALIAS, "tasks " + std::to_string(all[i].task) + " and " +
+                                         std::to_string(all[j].task) + " overlap");
+        }
+    }
+    pre[ntasks] = r.tiles;
+    hdr[0] = ntasks;
+    hdr[1] = r.tiles;
+    *info = r;
+    return FDBB_OK;
 }
 
 // Validate tasks and fill the plan's pinned staging copy.
@@ -791,61 +895,24 @@ int stage_tasks(fdbb_batch_plan *p, const fdbb_task *tasks, int ntasks)
 {
     if (ntasks < 0 || ntasks > p->capacity) return fail(FDBB_EINVAL, "ntasks exceeds the plan capacity");
     if (ntasks > 0 && !tasks) return fail(FDBB_EINVAL, "tasks must not be NULL");
-    std::vector<Call> calls((size_t)ntasks);
-    std::vector<Range> all;
-    size_t need_lds = 0;
-    for (int b = 0; b < ntasks; ++b) {
-        if (!batchable(tasks[b].op))
-            return fail(FDBB_EINVAL, "task " + std::to_string(b) + ": op not available in batches");
-        int rc = build_call(calls[b], tasks[b]);
-        if (rc) return fail(rc, "task " + std::to_string(b) + ": " + g_last_error);
-        rc = check_alias(calls[b]);
-        if (rc) return fail(rc, "task " + std::to_string(b) + ": " + g_last_error);
-        if (vector_ok(calls[b])) calls[b].a.flags |= kFlagVector;
-        const bool jac = tasks[b].op == FDBB_OP_FLUX_JACOBIAN || (tasks[b].op == FDBB_OP_FUSED && tasks[b].out1);
-        if (jac) need_lds = std::max(need_lds, lds_bytes(tasks[b].op, tasks[b].dim, tasks[b].dtype, p->block, p->ppt));
-        for (Range r : calls[b].ranges) {
-            r.task = b;
-            all.push_back(r);
-        }
-    }
-    if (need_lds > p->lds) return fail(FDBB_EINVAL, "tasks need more LDS than the plan was created with");
-    // Across tasks: no output may overlap another task's input or output.
-    std::sort(all.begin(), all.end(), [](const Range &x, const Range &y) { return x.lo < y.lo; });
-    for (size_t i = 0; i < all.size(); ++i) {
-        for (size_t j = i + 1; j < all.size() && all[j].lo < all[i].hi; ++j) {
-            if (all[i].task == all[j].task) continue;
-            if (all[i].input && all[j].input) continue;
-            return fail(FDBB_EALIAS, "tasks " + std::to_string(all[i].task) + " and " +
-                                         std::to_string(all[j].task) + " overlap");
-        }
-    }
+    // Fill a private copy first, so that a rejected list neither waits for
+    // nor disturbs an upload still reading the staging copy.
+    std::vector<unsigned char> tmp(p->bytes);
+    std::vector<Range> all((size_t)ntasks * 8);
+    TableInfo info;
+    int rc = fill_table(tasks, ntasks, p->capacity, p->block, p->ppt, tmp.data(), all.data(), &info);
+    if (rc) return rc;
+    if (info.lds > p->lds) return fail(FDBB_EINVAL, "tasks need more LDS than the plan was created with");
     // The previous upload must have consumed the staging copy.
     if (p->uploaded) {
         hipError_t e = hipEventSynchronize(p->uploaded);
         if (e != hipSuccess) return fail_hip(e, "hipEventSynchronize");
     }
-    int64_t *hdr = p->header(p->host);
-    int64_t *pre = p->prefix(p->host);
-    TaskDev *td = p->tasks(p->host);
-    const int64_t tile_pts = (int64_t)p->block * p->ppt;
-    int64_t tiles = 0, points = 0;
-    for (int b = 0; b < ntasks; ++b) {
-        pre[b] = tiles;
-        tiles += (tasks[b].n + tile_pts - 1) / tile_pts;
-        points += tasks[b].n;
-        td[b].a = calls[b].a;
-        td[b].op = tasks[b].op;
-        td[b].dim = tasks[b].dim;
-        td[b].dtype = tasks[b].dtype;
-        td[b].pad = 0;
-    }
-    pre[ntasks] = tiles;
-    hdr[0] = ntasks;
-    hdr[1] = tiles;
+    const size_t used = table_task_offset(p->capacity) + (size_t)ntasks * sizeof(TaskDev);
+    std::memcpy(p->host, tmp.data(), used);
     p->ntasks = ntasks;
-    p->tiles = tiles;
-    p->points = points;
+    p->tiles = info.tiles;
+    p->points = info.points;
     return FDBB_OK;
 }
 
@@ -930,7 +997,7 @@ int fdbb_batch_plan_create(const fdbb_task *tasks, int ntasks, int capacity, int
         return rc;
     }
     p->grid = grid > 0 ? grid : dev.cus * std::max(1, 2048 / block);
-    p->bytes = plan_bytes(capacity);
+    p->bytes = table_bytes(capacity);
     hipError_t e = hipMalloc((void **)&p->dev, p->bytes);
     if (e != hipSuccess) {
         free_plan(p);

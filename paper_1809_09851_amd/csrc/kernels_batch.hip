@@ -14,7 +14,8 @@ __device__ __forceinline__ void run_tile(int op, const Args &a, int64_t tile0, u
     case 0: tile_cons2prim<D, T, P, NT>(a, tile0); break;
     case 1: tile_prim2cons<D, T, P, NT>(a, tile0); break;
     case 2: tile_eos<D, T, P, NT>(a, tile0); break;
-    case 3: tile_flux<D, T, P, NT>(a, tile0); break;
+    case 3:
+    case 16: tile_flux<D, T, P, NT>(a, tile0); break;
     case 4:
     case 8: tile_fused<D, T, P, NT>(a, tile0, reinterpret_cast<T *>(smem)); break;
     case 5: tile_riemann<D, T, P, NT>(a, tile0); break;

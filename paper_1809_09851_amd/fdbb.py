@@ -28,7 +28,7 @@ OPS = {
     "cons2prim": 0, "prim2cons": 1, "eos": 2, "flux": 3, "flux_jacobian": 4,
     "riemann_invariants": 5, "cons2char": 6, "char2cons": 7, "fused": 8, "adjoint": 9,
     "v_mag2": 10, "eigenvectors": 11, "char_apply": 12, "roe_average": 13,
-    "eos_pvt": 14, "viscous_flux": 15,
+    "eos_pvt": 14, "viscous_flux": 15, "flux_dir": 16,
 }
 EOS_IDS = {"perfect_gas": 0, "stiffened_gas": 1}
 ROW_ALIGN = 64  # elements; keeps every row 16-byte aligned for both dtypes
@@ -84,6 +84,7 @@ def library():
                      "fdbb_riemann_invariants"):
             getattr(lib, name).argtypes = two
         lib.fdbb_eos.argtypes = [_i, _d, _i, _p, _i64, _p, _p, _i64, _p]
+        lib.fdbb_flux_direction.argtypes = [_i, _i, _d, _i, _p, _i64, _p, _i64, _i64, _p]
         lib.fdbb_velocity_magnitude2.argtypes = [_i, _i, _p, _i64, _p, _i64, _p]
         for name in ("fdbb_cons2char", "fdbb_char2cons"):
             getattr(lib, name).argtypes = [_i, _i, _d, _i, _p, _i64, _p, _i64, _i64, _p]
@@ -255,6 +256,14 @@ def fdbb_flux(dim, gamma, U, F, n=None, stream=None):
     check(library().fdbb_flux(dim, gamma, dtype_code(U.dtype), u, ldu, f, ldf, n, _stream(stream)))
 
 
+def fdbb_flux_direction(dim, direction, gamma, U, Fd, n=None, stream=None):
+    u, ldu = _fields(U, dim + 2, "U")
+    f, ldf = _fields(Fd, dim + 2, "Fd")
+    n = U.shape[1] if n is None else n
+    check(library().fdbb_flux_direction(dim, direction, gamma, dtype_code(U.dtype), u, ldu, f, ldf, n,
+                                        _stream(stream)))
+
+
 def fdbb_flux_jacobian(dim, gamma, U, A, n=None, stream=None):
     u, ldu = _fields(U, dim + 2, "U")
     a, lda = _blocks(A, dim)
@@ -413,8 +422,13 @@ def eos(U, gamma=1.4, stream=None):
     return p, c
 
 
-def flux(U, gamma=1.4, stream=None):
+def flux(U, gamma=1.4, stream=None, direction=None):
+    """The flux tensor (K*D fields), or F_direction alone (K fields)."""
     dim = _dim_of(U)
+    if direction is not None:
+        Fd = empty_fields(dim + 2, U.shape[1], U.dtype, U.device)
+        fdbb_flux_direction(dim, direction, gamma, U, Fd, stream=stream)
+        return Fd
     F = empty_fields((dim + 2) * dim, U.shape[1], U.dtype, U.device)
     fdbb_flux(dim, gamma, U, F, stream=stream)
     return F

@@ -108,6 +108,15 @@ def test_direction_checks():
     assert lib.fdbb_flux_adjoint(3, -2, 1.4, 0, A0, 128, B0, 128, A0 + 10**7, 128, 100, None) == F.EINVAL
 
 
+def test_flux_direction_checks():
+    lib = F.library()
+    assert lib.fdbb_flux_direction(3, 3, 1.4, 0, A0, 128, B0, 128, 100, None) == F.EINVAL
+    assert lib.fdbb_flux_direction(2, -1, 1.4, 0, A0, 128, B0, 128, 100, None) == F.EINVAL
+    assert lib.fdbb_flux_direction(3, 0, 1.4, 0, A0, 128, B0, 64, 100, None) == F.EINVAL  # ld < n
+    assert lib.fdbb_flux_direction(3, 1, 1.4, 0, A0, 128, A0 + 8 * 64, 128, 100, None) == F.EALIAS
+    assert lib.fdbb_flux_direction(1, 0, 1.4, 0, A0, 128, B0, 128, 0, None) == F.OK
+
+
 def test_eigen_and_char_apply_checks():
     lib = F.library()
     assert lib.fdbb_eigenvectors(3, 1.4, 0, A0, 128, None, 0, None, 0, 100, None) == F.EINVAL

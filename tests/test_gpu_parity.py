@@ -120,8 +120,20 @@ def test_characteristic_transforms(dim, dt, n):
         # inverse, on the exact W the GPU holds
         Wh = host(W)
         U2 = F.char2cons(W, d, GAMMA)
-        tol = 1e-11 if dt == "f64" else 1e-5
-        assert group_error(host(U2), oracle.char2cons(dim, d, GAMMA, Wh), state_groups(dim)) <= tol
+        assert group_error(host(U2), oracle.char2cons(dim, d, GAMMA, Wh), state_groups(dim)) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("dim", DIMS)
+@pytest.mark.parametrize("n", SIZES)
+def test_flux_direction(dim, dt, n):
+    """F_d alone equals column d of the oracle's flux block (fields r*D + d)."""
+    Uo, Ug = states(dim, n, _seed(dim, n, dt, 8), dt)
+    Fo = oracle.flux(dim, GAMMA, Uo)
+    for d in range(dim):
+        Fd = F.flux(Ug, GAMMA, direction=d)
+        assert Fd.shape == (dim + 2, n)
+        assert group_error(host(Fd), Fo[d::dim], [list(range(dim + 2))]) <= TOL[dt]
 
 
 @pytest.mark.parametrize("dt", DTS)
