@@ -328,6 +328,25 @@ int fdbb_batch_plan_info(const fdbb_batch_plan *plan, int64_t *points, int64_t *
  * it is still running). */
 int fdbb_batch_plan_destroy(fdbb_batch_plan *plan);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): one persistent batch launch of `tasks`
+ * with the meaning of fdbb_batch_plan_create + fdbb_batch_exec(use_graph =
+ * 0), without a plan.  Allocates nothing: the task table goes into a fixed
+ * device array of the library, one per device (about 230 KB, held until the
+ * process ends), with room for FDBB_NOALLOC_MAX_TASKS tasks; more tasks give
+ * FDBB_EINVAL.  Tasks, block (64..256), ppt, grid (0 picks one sized to the
+ * device) and nontemporal are validated as for a plan, with the same
+ * statuses; each call uploads only its own table, nothing needs clearing.
+ * The table is copied from the library's static host staging array, a copy
+ * that HIP completes before returning (pageable host memory), so the call
+ * waits for the work already queued on `stream`; it is therefore not for
+ * use under stream capture.  The kernel reads the table when it runs: calls
+ * on one stream are ordered, but calls on one device that overlap in time
+ * from different streams race on the shared table. */
+#define FDBB_NOALLOC_MAX_TASKS 1024
+int fdbb_batch_run_noalloc(const fdbb_task *tasks, int ntasks, int block, int ppt, int grid,
+                           int nontemporal, void *stream);
+
 /* ---------------------------------------------------------------- misc */
 const char *fdbb_status_string(int status);
 /* Text of the last error reported on the calling thread ("" if none). */

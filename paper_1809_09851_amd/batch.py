@@ -2,8 +2,10 @@
 
 A ``Plan`` wraps ``fdbb_batch_plan_*``: the task table lives on the device,
 one persistent kernel walks every tile of every task, and that launch is
-captured once in a HIP graph and replayed.  Task builders take the same
-tensors as the single-call functions in ``fdbb``.
+captured once in a HIP graph and replayed.  ``run_noalloc`` is the same
+launch without a plan (``fdbb_batch_run_noalloc``: the table goes into the
+library's fixed device array, nothing is allocated).  Task builders take
+the same tensors as the single-call functions in ``fdbb``.
 """
 from __future__ import annotations
 
@@ -96,6 +98,17 @@ def riemann_task(U, R, gamma=1.4):
     _set(t, "in0", U, dim + 2)
     _set(t, "out0", R, 2 * dim + 1)
     return t
+
+
+MAX_NOALLOC_TASKS = 1024  # FDBB_NOALLOC_MAX_TASKS
+
+
+def run_noalloc(tasks, block=256, ppt=1, grid=0, nontemporal=1, stream=None):
+    """One persistent launch of ``tasks`` through the allocation-free entry
+    point (at most MAX_NOALLOC_TASKS tasks)."""
+    arr = (F.Task * max(1, len(tasks)))(*tasks)
+    F.check(F.library().fdbb_batch_run_noalloc(arr, len(tasks), block, ppt, grid, nontemporal,
+                                               F._stream(stream)))
 
 
 class Plan:

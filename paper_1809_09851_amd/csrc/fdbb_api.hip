@@ -1090,4 +1090,51 @@ int fdbb_batch_plan_destroy(fdbb_batch_plan *plan)
     return FDBB_OK;
 }
 
+int fdbb_batch_run_noalloc(const fdbb_task *tasks, int ntasks, int block, int ppt, int grid, int nontemporal,
+                           void *stream)
+{
+    g_last_error.clear();
+    if (ntasks < 0 || ntasks > FDBB_NOALLOC_MAX_TASKS)
+        return fail(FDBB_EINVAL, "the allocation-free batch takes 0 to " + std::to_string(FDBB_NOALLOC_MAX_TASKS) +
+                                     " tasks, got " + std::to_string(ntasks));
+    if (!config_ok(block, ppt, grid, nontemporal) || block > kMaxBlockStaged)
+        return fail(FDBB_EINVAL, "invalid launch configuration (batches take at most 256 threads per workgroup)");
+    if (ntasks > 0 && !tasks) return fail(FDBB_EINVAL, "tasks must not be NULL");
+    DeviceInfo dev;
+    int rc = device_info(&dev);
+    if (rc) return rc;
+    // Host staging of the table and the range list of the overlap check:
+    // static, so this call uses no heap; the lock makes concurrent callers
+    // take turns over them.
+    static std::mutex staging_mutex;
+    alignas(64) static unsigned char staging[kNoAllocBytes];
+    static Range ranges[8 * (size_t)kNoAllocMaxTasks];
+    std::lock_guard<std::mutex> lock(staging_mutex);
+    TableInfo info;
+    rc = fill_table(tasks, ntasks, kNoAllocMaxTasks, block, ppt, staging, ranges, &info);
+    if (rc) return rc;
+    if (info.tiles == 0) return FDBB_OK;
+    void *table = nullptr;
+    const int se = batch_scratch(&table);
+    if (se) return fail_hip((hipError_t)se, "hipGetSymbolAddress of the batch task table");
+    const void *kernel = kernel_batch(ppt, nontemporal != 0);
+    if (!kernel) return fail(FDBB_EINVAL, "no batch kernel for this configuration");
+    if ((rc = set_lds_attr(kernel, info.lds, dev))) return rc;
+    // From pageable host memory the copy completes before the call returns,
+    // so the staging array is free again once it does; it is ordered on
+    // `stream` before the launch that reads the table.
+    const size_t used = table_task_offset(kNoAllocMaxTasks) + (size_t)ntasks * sizeof(TaskDev);
+    hipError_t e = hipMemcpyAsync(table, staging, used, hipMemcpyHostToDevice, (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync");
+    unsigned char *base = static_cast<unsigned char *>(table);
+    const TaskDev *dtasks = table_tasks(base, kNoAllocMaxTasks);
+    const int64_t *prefix = table_prefix(base);
+    const int64_t *header = table_header(base);
+    void *args[] = {&dtasks, &prefix, &header};
+    const int g = grid > 0 ? grid : dev.cus * std::max(1, 2048 / block);
+    e = hipLaunchKernel(kernel, dim3((unsigned)g), dim3((unsigned)block), args, info.lds, (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "batch kernel launch");
+    return FDBB_OK;
+}
+
 }  // extern "C"

@@ -60,4 +60,16 @@ const void *kernel_eigen(int family, int dim, int dtype, int ppt, bool nt);
 // entries, prefix[b] = first tile of task b.
 const void *kernel_batch(int ppt, bool nt);
 
+// The allocation-free batch entry point's fixed task table: room for
+// kNoAllocMaxTasks tasks in the layout of a plan's table (header, tile
+// prefix sums, task images).
+constexpr int kNoAllocMaxTasks = 1024;
+constexpr size_t kNoAllocBytes =
+    (((2 + (size_t)kNoAllocMaxTasks + 1) * sizeof(int64_t) + 63) & ~(size_t)63) + (size_t)kNoAllocMaxTasks * sizeof(TaskDev);
+
+// Device address of that table on the current device (looked up with
+// hipGetSymbolAddress on a device's first call, then cached); 0 or a
+// hipError_t.
+int batch_scratch(void **ptr);
+
 }  // namespace fdbb

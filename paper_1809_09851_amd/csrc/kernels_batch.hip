@@ -5,6 +5,8 @@
 // same, so the static deal balances without a shared counter.
 #include "fdbb_internal.hpp"
 
+#include <atomic>
+
 namespace fdbb {
 
 template <int D, typename T, int P, int NT>
@@ -56,6 +58,33 @@ __global__ __launch_bounds__(kMaxBlockStaged) void k_batch(const TaskDev *__rest
             else run_tile<3, float, P, NT>(td.op, td.a, tile0, smem);
         }
     }
+}
+
+// Task table of the allocation-free batch entry point: one fixed array per
+// device, holding the table layout of a plan of capacity kNoAllocMaxTasks.
+// Host code never passes `scratch` itself (in host code the name is a
+// host-side stand-in, not a device address): batch_scratch looks up the
+// device address once per device and every caller uses that.
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+int batch_scratch(void **ptr)
+{
+    static std::atomic<uintptr_t> addr[64];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    if (dev < 0 || dev >= 64) return (int)hipErrorInvalidDevice;
+    uintptr_t a = addr[dev].load(std::memory_order_acquire);
+    if (a == 0) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return (int)e;
+        if (p == nullptr) return (int)hipErrorInvalidSymbol;
+        a = (uintptr_t)p;
+        addr[dev].store(a, std::memory_order_release);
+    }
+    *ptr = (void *)a;
+    return 0;
 }
 
 const void *kernel_batch(int ppt, bool nt)

@@ -110,6 +110,7 @@ def library():
         lib.fdbb_batch_exec.argtypes = [_p, _p, _i]
         lib.fdbb_batch_plan_info.argtypes = [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
         lib.fdbb_batch_plan_destroy.argtypes = [_p]
+        lib.fdbb_batch_run_noalloc.argtypes = [ctypes.POINTER(Task), _i, _i, _i, _i, _i, _p]
         lib.fdbb_task_check.argtypes = [ctypes.POINTER(Task)]
         lib.fdbb_task_run.argtypes = [ctypes.POINTER(Task), _p]
         lib.fdbb_server_create.argtypes = [_i64, _i, _i, _d, _i, ctypes.POINTER(_p)]

@@ -117,6 +117,18 @@ def test_flux_direction_checks():
     assert lib.fdbb_flux_direction(1, 0, 1.4, 0, A0, 128, B0, 128, 0, None) == F.OK
 
 
+def test_noalloc_batch_rejects_before_any_hip_call():
+    lib = F.library()
+    t = (F.Task * 1)()
+    t[0].op, t[0].dim, t[0].dtype, t[0].gamma, t[0].n = F.OPS["flux"], 3, 0, 1.4, 0
+    assert lib.fdbb_batch_run_noalloc(t, 1025, 256, 1, 0, 1, None) == F.EINVAL
+    assert b"1024" in lib.fdbb_last_error()
+    assert lib.fdbb_batch_run_noalloc(t, -1, 256, 1, 0, 1, None) == F.EINVAL
+    assert lib.fdbb_batch_run_noalloc(t, 1, 512, 1, 0, 1, None) == F.EINVAL
+    assert lib.fdbb_batch_run_noalloc(t, 1, 256, 3, 0, 1, None) == F.EINVAL
+    assert lib.fdbb_batch_run_noalloc(None, 2, 256, 1, 0, 1, None) == F.EINVAL
+
+
 def test_eigen_and_char_apply_checks():
     lib = F.library()
     assert lib.fdbb_eigenvectors(3, 1.4, 0, A0, 128, None, 0, None, 0, 100, None) == F.EINVAL
