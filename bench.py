@@ -44,6 +44,58 @@ def measured_traffic(n: int):
     return traffic.load_bytes_per_launch(PROFILE_TRAFFIC, n)
 
 
+def box_state(root: str = "/sys/class/drm"):
+    """The GPU's clock, power and partition settings from sysfs (read-only
+    files of the amdgpu driver), so that a bench line says which machine
+    state it was measured in.  Missing files are left out."""
+    import glob
+
+    def read(path):
+        try:
+            with open(path) as f:
+                return f.read().strip()
+        except OSError:
+            return None
+
+    def current_level(text):
+        # "0: 2000Mhz *" -> "2000Mhz" (the level marked current)
+        for ln in (text or "").splitlines():
+            if ln.strip().endswith("*"):
+                return ln.split(":", 1)[1].replace("*", "").strip()
+        return None
+
+    for dev in sorted(glob.glob(os.path.join(root, "card*", "device"))):
+        if read(os.path.join(dev, "vendor")) != "0x1002":
+            continue
+        out = {"pci": os.path.basename(os.path.realpath(dev))}
+        mp = read(os.path.join(dev, "current_memory_partition"))
+        cp = read(os.path.join(dev, "current_compute_partition"))
+        if mp:
+            out["memory_partition"] = mp
+        if cp:
+            out["compute_partition"] = cp
+        mclk = current_level(read(os.path.join(dev, "pp_dpm_mclk")))
+        if mclk:
+            out["hbm_clock"] = mclk
+        sclk = read(os.path.join(dev, "pp_dpm_sclk"))
+        if sclk:
+            levels = [ln.split(":", 1)[1].replace("*", "").strip() for ln in sclk.splitlines() if ":" in ln]
+            out["gfx_clock_levels"] = levels
+        perf = read(os.path.join(dev, "power_dpm_force_performance_level"))
+        if perf:
+            out["performance_level"] = perf
+        for hw in sorted(glob.glob(os.path.join(dev, "hwmon", "hwmon*"))):
+            cap = read(os.path.join(hw, "power1_cap"))
+            if cap and cap.isdigit():
+                out["power_cap_w"] = int(cap) / 1e6
+                break
+        vram = read(os.path.join(dev, "mem_info_vram_total"))
+        if vram and vram.isdigit():
+            out["vram_gib"] = round(int(vram) / 2 ** 30, 1)
+        return out
+    return None
+
+
 def timed_launches(fn, steps: int, warmup: int):
     """Run fn() warmup + steps times; returns (wall ms per step, mean HIP-event
     ms per launch), events recorded on the stream the kernels run on."""
@@ -285,8 +337,20 @@ def bench_serving(rates, count: int, warmup: int, slots: int = 8, batch_mb: floa
                       f"p50 {r['p50_ms']} ms p99 {r['p99_ms']} ms, {r['req_s']} req/s",
                       file=sys.stderr, flush=True)
                 out.append(r)
+    # saturating load: a fixed number of requests outstanding, so that the
+    # device never waits for arrivals and the two modes' throughput differs
+    sat = {}
+    if engine in ("native", "both"):
+        for baseline in (False, True):
+            mode = "single" if baseline else "batched"
+            r = S.native_serve_closed_loop(count, concurrency=64, warmup=warmup, pools=pools, slots=slots,
+                                           mode=mode, budget=budget, max_batch_bytes=batch_mb * 1e6)
+            print(f"# serving saturated ({r['concurrency']} outstanding) {mode}: {r['req_s']} req/s, "
+                  f"{r['gpoints_s']} Gpoints/s, p50 {r['p50_ms']} ms p99 {r['p99_ms']} ms",
+                  file=sys.stderr, flush=True)
+            sat[mode] = r
     del pools
-    return out
+    return out, sat
 
 
 def bench_batched(steps: int, warmup: int, dtype, nblocks: int = 512):
@@ -490,6 +554,7 @@ def main(argv=None):
               "use --gpus 1", file=sys.stderr)
         return 2
 
+    box = box_state()  # before the process's first GPU call
     import torch
     from paper_1809_09851_amd import fdbb as F
     if not os.path.exists(F.LIBRARY):
@@ -524,6 +589,8 @@ def main(argv=None):
                      "traffic": traffic,
                      "bytes_per_point": fused_bytes(3, 8), "kernel_ms": round(main_run["kernel_ms"], 4)},
     }
+    if box:
+        line["box"] = box
     # the device's own ceiling for a plain write stream (95 % of the fused
     # pass's bytes are writes), measured in the same process
     ceiling = write_ceiling()
@@ -550,8 +617,11 @@ def main(argv=None):
         line["paper_sweeps"] = bench_paper_sweeps()
     rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
     if rates:
-        line["serving"] = bench_serving(rates, args.serve_count, args.serve_warmup, args.serve_slots,
-                                        args.serve_batch_mb, args.serve_engine)
+        sweep, sat = bench_serving(rates, args.serve_count, args.serve_warmup, args.serve_slots,
+                                   args.serve_batch_mb, args.serve_engine)
+        line["serving"] = sweep
+        if sat:
+            line["serving_saturated"] = sat
     if args.probe_copy:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
         b = torch.empty_like(a)

@@ -566,3 +566,53 @@ def native_serve_benchmark(rate: float, count: int, warmup: int = 200, slots: in
             "mode": ("native server, continuous batching, " f"{slots} slots, <= {max_batch} requests and "
                      f"<= {max_batch_bytes / 1e6:g} MB per launch") if mode == "batched" else
                     "native server, one launch per request, FIFO, single stream"}
+
+
+def native_serve_closed_loop(count: int, concurrency: int = 64, warmup: int = 200, slots: int = 8,
+                             max_batch: int = 64, budget: int = 200 * 10 ** 9, pools: StatePools | None = None,
+                             mode: str = "batched", seed: int = 4, max_batch_bytes: float = 64e6):
+    """Saturating load: the serving workload's request mix with `concurrency`
+    requests outstanding at all times (a new one is submitted as soon as one
+    completes), so the device never waits for arrivals.  Throughput counts
+    completions over the span from the first measured submission to the last
+    measured completion; latency runs from submission to completion (the
+    server's clock).  The first `warmup` requests are not measured."""
+    import numpy as np
+
+    from . import inputs
+    pools = pools or StatePools()
+    specs = inputs.request_stream(1.0, warmup + count, seed=seed, pool=pools.pool)
+    reqs = [pools.request(s) for s in specs]
+    tasks = [request_task(r) for r in reqs]
+    srv = NativeServer(budget, slots=slots, max_batch=max_batch, max_batch_bytes=max_batch_bytes, mode=mode)
+    sub, done = {}, {}
+    k = 0
+    while k < min(concurrency, len(reqs)):
+        srv.submit(tasks[k], k)
+        k += 1
+    while len(done) < len(reqs):
+        for c in srv.poll():
+            if c.status != 0:
+                raise RuntimeError(f"request {c.tag} failed")
+            sub[c.tag] = c.t_submit_ns
+            done[c.tag] = c.t_done_ns
+            srv.release(c.tag)
+            if k < len(reqs):
+                srv.submit(tasks[k], k)
+                k += 1
+    st = srv.stats()
+    srv.close()
+    ids = range(warmup, warmup + count)
+    lat = np.array([(done[i] - sub[i]) * 1e-9 for i in ids])
+    span = (max(done[i] for i in ids) - min(sub[i] for i in ids)) * 1e-9
+    pts = sum(reqs[i].n for i in ids)
+    moved = sum(moved_bytes(reqs[i].op, reqs[i].dim, reqs[i].n, reqs[i].elem) for i in ids)
+    return {"requests": count, "concurrency": concurrency, "seconds": round(span, 4),
+            "req_s": round(count / span, 1), "gpoints_s": round(pts / span / 1e9, 3),
+            "gb_s": round(moved / span / 1e9, 1),
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4),
+            "launches": st["launches"], "peak_budget_bytes": st["peak_arena_bytes"],
+            "mode": ("native server, continuous batching, " f"{slots} slots, <= {max_batch} requests and "
+                     f"<= {max_batch_bytes / 1e6:g} MB per launch") if mode == "batched" else
+                    "native server, one launch per request, FIFO, single stream"}

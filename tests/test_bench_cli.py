@@ -53,3 +53,26 @@ def test_traffic_record_from_counter_files(tmp_path):
     rec = traffic.build_record("k_fused", paths["fetch"], paths["write"], n)
     assert abs(rec["fetch_scale"] - 2.0) < 1e-12 and abs(rec["write_scale"] - 1.0) < 1e-12
     assert abs(rec["bytes_per_launch"] - 816 * n) < 1e-6 * 816 * n
+
+
+def test_box_state_reads_the_driver_files(tmp_path):
+    sys.path.insert(0, ROOT)
+    import bench
+    dev = tmp_path / "card0" / "device"
+    (dev / "hwmon" / "hwmon3").mkdir(parents=True)
+    (dev / "vendor").write_text("0x1002\n")
+    (dev / "current_memory_partition").write_text("NPS1\n")
+    (dev / "current_compute_partition").write_text("SPX\n")
+    (dev / "pp_dpm_mclk").write_text("0: 900Mhz \n1: 2000Mhz *\n")
+    (dev / "pp_dpm_sclk").write_text("0: 500Mhz \n1: 158Mhz *\n2: 2400Mhz \n")
+    (dev / "hwmon" / "hwmon3" / "power1_cap").write_text("1400000000\n")
+    (dev / "mem_info_vram_total").write_text(str(288 * 2 ** 30) + "\n")
+    other = tmp_path / "card1" / "device"
+    other.mkdir(parents=True)
+    (other / "vendor").write_text("0x8086\n")
+    s = bench.box_state(str(tmp_path))
+    assert s["memory_partition"] == "NPS1" and s["compute_partition"] == "SPX"
+    assert s["hbm_clock"] == "2000Mhz"
+    assert s["gfx_clock_levels"] == ["500Mhz", "158Mhz", "2400Mhz"]
+    assert s["power_cap_w"] == 1400.0 and s["vram_gib"] == 288.0
+    assert bench.box_state(str(tmp_path / "none")) is None
