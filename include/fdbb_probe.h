@@ -47,16 +47,17 @@ int fdbb_probe_fused_stores(double *F, double *R, double *A, int64_t n, void *st
 /* The power x^y = exp(y log x) that the building blocks take for the
  * entropy p / rho^gamma and for rho from the entropy, evaluated on the
  * device for out[i] = x[i]^y[i], i < n, with the same device functions:
- * short_series = 0 selects the library's exp and log (the FP64-storage
- * kernels), nonzero the short FP64 series of the FP32-storage kernels
- * (relative error below 5e-14 for x in [e^-12, e^12], |y| <= 3).  Zero,
- * negative and non-finite x give what exp(y log x) gives in IEEE
- * arithmetic.  Exposed so the accuracy of the shared power can be checked
- * apart from the building blocks.  Unlike the streaming probes, accesses
- * are 8 bytes per lane with regular stores; the arrays are FP64 device
- * arrays of n elements, 8-byte aligned (FDBB_EINVAL for NULL, misaligned
- * pointers or n < 0; n = 0 launches nothing). */
-int fdbb_probe_pow(const double *x, const double *y, double *out, int64_t n, int short_series, void *stream);
+ * fp32_form = 0 selects the library's exp and log (the FP64-storage
+ * kernels, relative error below 1e-14 for |y log x| < 40), nonzero the
+ * base-2 form of the FP32-storage kernels (FP64 exponent split and scaling,
+ * hardware FP32 log2 and exp2 of the reduced arguments; relative error
+ * below 6e-7 for |y| <= 3).  Zero, negative and non-finite x give what
+ * exp(y log x) gives in IEEE arithmetic.  Exposed so the accuracy of the
+ * shared power can be checked apart from the building blocks.  Unlike the
+ * streaming probes, accesses are 8 bytes per lane with regular stores; the
+ * arrays are FP64 device arrays of n elements, 8-byte aligned (FDBB_EINVAL
+ * for NULL, misaligned pointers or n < 0; n = 0 launches nothing). */
+int fdbb_probe_pow(const double *x, const double *y, double *out, int64_t n, int fp32_form, void *stream);
 
 #ifdef __cplusplus
 }

@@ -230,83 +230,50 @@ __device__ __forceinline__ Waves make_waves(const Gas &g, const State<D> &s)
 // 1e-14 for |y log x| < 40).  x <= 0 gives NaN or the limit at 0, as pow.
 __device__ __forceinline__ double pos_pow(double x, double y) { return exp(y * log(x)); }
 
-// The same power with shorter series, for outputs stored in FP32, where
-// the library's exp and log make the entropy-carrying transforms bound by
-// the FP64 instruction rate rather than by HBM.  Still FP64 throughout:
-// relative error below 5e-14 (x = e^-12..e^12, |y| <= 3), far under the
-// 6e-8 rounding of the FP32 store.  Zero, negative and non-finite
-// arguments give the IEEE results of log and exp (selected, not branched,
-// so the library code and its registers stay out of the kernel); results
-// beyond the range of doubles saturate to inf or 0, subnormal ones are
-// formed by the final scaling.
-
-// log x: for finite x > 0, x = m 2^e with m in [sqrt(1/2), sqrt(2)), and
-// log m = 2 atanh(t) with t = (m - 1)/(m + 1), |t| < 0.1716, summed as the
-// odd series 2 (t + t^3/3 + ... + t^15/15); ln 2 in two parts.
-__device__ __forceinline__ double log_short(double x)
+// The same power for outputs stored in FP32, where the library's FP64 exp
+// and log would make the entropy-carrying transforms bound by the FP64
+// instruction rate rather than by HBM.  Base-2 decomposition:
+//   x = m 2^e (frexp, exact; m in [1/2, 1)),
+//   z = y (e + log2 m),  z = k + f (k = floor z, f in [0, 1)),
+//   x^y = 2^f 2^k,
+// with log2 m and 2^f from the GPU's FP32 transcendental instructions
+// (v_log_f32, v_exp_f32, each within about one unit in the last place),
+// and the exponent split, the sum e + log2 m, the product with y and the
+// scaling by 2^k in FP64.  Relative error: |y| ln 2 (2^-24 / ln 2 + 2^-24)
+// from the FP32 rounding of m and the logarithm, plus 2^-24 ln 2 + 2^-23
+// from f and the exponential, below 6e-7 for |y| <= 3; the building blocks
+// take y = -gamma and y = 1/(gamma-1), and the FP32-storage contract is
+// 1e-5.  Zero, negative and non-finite x give what exp(y log x) gives in
+// IEEE arithmetic (selected, not branched, so no library code enters the
+// kernels); results beyond the range of doubles saturate to inf or 0.
+__device__ __forceinline__ double pos_pow_fp32(double x, double y)
 {
     const bool ok = x > 0.0 && x < INFINITY;
     int e;
-    double m = frexp(ok ? x : 1.0, &e);
-    if (m < 0.70710678118654752440) {
-        m *= 2.0;
-        --e;
-    }
-    const double t = (m - 1.0) / (m + 1.0);
-    const double t2 = t * t;
-    double p = 1.0 / 15.0;
-    p = fma(p, t2, 1.0 / 13.0);
-    p = fma(p, t2, 1.0 / 11.0);
-    p = fma(p, t2, 1.0 / 9.0);
-    p = fma(p, t2, 1.0 / 7.0);
-    p = fma(p, t2, 1.0 / 5.0);
-    p = fma(p, t2, 1.0 / 3.0);
-    p = fma(p, t2, 1.0);
-    const double ln2_hi = 6.93147180369123816490e-01, ln2_lo = 1.90821492927058770002e-10;
-    const double r = fma((double)e, ln2_hi, fma((double)e, ln2_lo, 2.0 * t * p));
-    // log 0 = -inf, log inf = inf, NaN below zero and for NaN
-    return ok ? r : (x == 0.0 ? -INFINITY : (x == INFINITY ? INFINITY : NAN));
+    const double m = frexp(ok ? x : 1.0, &e);
+    const double l2 = (double)e + (double)__builtin_amdgcn_logf((float)m);
+    // log2 0 = -inf, log2 inf = inf, NaN below zero and for NaN
+    const double lg = ok ? l2 : (x == 0.0 ? -INFINITY : (x == INFINITY ? INFINITY : NAN));
+    const double z = y * lg;
+    const double zc = fmin(fmax(z, -1100.0), 1100.0);  // 2^k saturates beyond
+    const double k = floor(zc);
+    const double r = ldexp((double)__builtin_amdgcn_exp2f((float)(zc - k)), (int)k);
+    return z != z ? z : r;
 }
 
-// e^z: z = k ln 2 + r with |r| <= ln 2 / 2 (ln 2 in two parts), e^r by
-// its Taylor series to degree 12, scaled by 2^k.
-__device__ __forceinline__ double exp_short(double z)
-{
-    // beyond +-800 the scaling by 2^k saturates to inf or 0, as exp does
-    const double zc = fmin(fmax(z, -800.0), 800.0);
-    const double k = rint(zc * 1.44269504088896340736);
-    const double ln2_hi = 6.93147180369123816490e-01, ln2_lo = 1.90821492927058770002e-10;
-    const double r = fma(-k, ln2_lo, fma(-k, ln2_hi, zc));
-    double p = 1.0 / 479001600.0;
-    p = fma(p, r, 1.0 / 39916800.0);
-    p = fma(p, r, 1.0 / 3628800.0);
-    p = fma(p, r, 1.0 / 362880.0);
-    p = fma(p, r, 1.0 / 40320.0);
-    p = fma(p, r, 1.0 / 5040.0);
-    p = fma(p, r, 1.0 / 720.0);
-    p = fma(p, r, 1.0 / 120.0);
-    p = fma(p, r, 1.0 / 24.0);
-    p = fma(p, r, 1.0 / 6.0);
-    p = fma(p, r, 0.5);
-    p = fma(p, r, 1.0);
-    p = fma(p, r, 1.0);
-    const double v = ldexp(p, (int)k);
-    return z != z ? z : v;
-}
-
-// x^y for x > 0: with the short series when SHORT (FP32 storage).
-template <bool SHORT>
+// x^y for x > 0: FP32-storage form when FP32 (outputs stored in FP32).
+template <bool FP32>
 __device__ __forceinline__ double pos_pow_t(double x, double y)
 {
-    if constexpr (SHORT) return exp_short(y * log_short(x));
+    if constexpr (FP32) return pos_pow_fp32(x, y);
     else return pos_pow(x, y);
 }
 
 // Entropy s = p / rho^gamma.
-template <int D, bool SHORT = false>
+template <int D, bool FP32 = false>
 __device__ __forceinline__ double entropy(const Gas &g, const State<D> &s)
 {
-    return s.p * pos_pow_t<SHORT>(s.rho, -g.gamma);
+    return s.p * pos_pow_t<FP32>(s.rho, -g.gamma);
 }
 
 // Adjoint contribution of direction d: ubar += A_d^T fb, where fb = (a,

@@ -71,16 +71,16 @@ __global__ __launch_bounds__(128) void k_fused_stores(double *__restrict__ F, do
 }
 
 // x^y = exp(y log x) for each element, by the library's exp and log
-// (SHORT false, the FP64-storage kernels) or by the short series of the
-// FP32-storage kernels (SHORT true): the same device functions the building
+// (FP32 false, the FP64-storage kernels) or by the base-2 form of the
+// FP32-storage kernels (FP32 true): the same device functions the building
 // blocks call.  One element per thread, grid-stride; regular stores.
-template <bool SHORT>
+template <bool FP32>
 __global__ __launch_bounds__(256) void k_pow(const double *__restrict__ x, const double *__restrict__ y,
                                             double *__restrict__ out, int64_t n)
 {
     const int64_t stride = (int64_t)gridDim.x * 256;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
-        out[i] = fdbb::pos_pow_t<SHORT>(x[i], y[i]);
+        out[i] = fdbb::pos_pow_t<FP32>(x[i], y[i]);
 }
 
 int grid_for(int grid)
@@ -140,7 +140,7 @@ int fdbb_probe_fused_stores(double *F, double *R, double *A, int64_t n, void *st
     return hipGetLastError() == hipSuccess ? FDBB_OK : FDBB_EHIP;
 }
 
-int fdbb_probe_pow(const double *x, const double *y, double *out, int64_t n, int short_series, void *stream)
+int fdbb_probe_pow(const double *x, const double *y, double *out, int64_t n, int fp32_form, void *stream)
 {
     if (!aligned8(x) || !aligned8(y) || !aligned8(out) || n < 0) return FDBB_EINVAL;
     if (n == 0) return FDBB_OK;
@@ -148,7 +148,7 @@ int fdbb_probe_pow(const double *x, const double *y, double *out, int64_t n, int
     if (cap <= 0) return FDBB_EHIP;
     const int64_t want = (n + 255) / 256;
     const unsigned g = (unsigned)(want < cap ? want : cap);
-    if (short_series)
+    if (fp32_form)
         hipLaunchKernelGGL(k_pow<true>, dim3(g), dim3(256), 0, (hipStream_t)stream, x, y, out, n);
     else
         hipLaunchKernelGGL(k_pow<false>, dim3(g), dim3(256), 0, (hipStream_t)stream, x, y, out, n);

@@ -498,17 +498,18 @@ def probe_fused_stores(F_: torch.Tensor, R: torch.Tensor, A: torch.Tensor, n: in
     check(library().fdbb_probe_fused_stores(_dptr(F_), _dptr(R), _dptr(A), n, _stream(stream)))
 
 
-def probe_pow(x: torch.Tensor, y: torch.Tensor, short_series: bool, stream=None) -> torch.Tensor:
+def probe_pow(x: torch.Tensor, y: torch.Tensor, fp32_form: bool, stream=None) -> torch.Tensor:
     """x ** y elementwise on the device, by the power the building blocks
-    use: the library's exp and log, or the short series of the FP32-storage
-    kernels.  x and y: contiguous FP64 device tensors of one shape."""
+    use: the library's exp and log (FP64 storage), or the base-2 form of the
+    FP32-storage kernels.  x and y: contiguous FP64 device tensors of one
+    shape."""
     if x.dtype != torch.float64 or y.dtype != torch.float64 or x.shape != y.shape:
         raise ValueError("probe_pow takes two FP64 tensors of one shape")
     if not (x.is_contiguous() and y.is_contiguous()):
         raise ValueError("probe_pow takes contiguous tensors")
     out = torch.empty_like(x)
     check(library().fdbb_probe_pow(_dptr(x), _dptr(y), _dptr(out), x.numel(),
-                                   1 if short_series else 0, _stream(stream)))
+                                   1 if fp32_form else 0, _stream(stream)))
     return out
 
 

@@ -69,6 +69,9 @@ def workload(op: str, dim: int, dtype, n: int):
     if op == "flux":
         Fo = F.empty_fields(K * dim, n, dtype)
         return lambda: F.fdbb_flux(dim, GAMMA, U, Fo)
+    if op == "flux_dir":
+        Fd = F.empty_fields(K, n, dtype)
+        return lambda: F.fdbb_flux_direction(dim, dim - 1, GAMMA, U, Fd)
     if op == "cons2prim":
         V = F.empty_fields(K, n, dtype)
         return lambda: F.fdbb_cons2prim(dim, GAMMA, U, V)
@@ -122,7 +125,7 @@ def bytes_per_point(op: str, dim: int, elem: int) -> int:
     """Algorithmic HBM bytes per point of one launch of `op`."""
     K = dim + 2
     per = {"cons2prim": 2 * K, "prim2cons": 2 * K, "cons2char": 2 * K, "char2cons": 2 * K,
-           "eos": K + 2, "v_mag2": dim + 2, "flux": K + K * dim, "flux_jacobian": K + dim * K * K,
+           "eos": K + 2, "v_mag2": dim + 2, "flux": K + K * dim, "flux_dir": 2 * K, "flux_jacobian": K + dim * K * K,
            "riemann_invariants": K + 2 * dim + 1, "fused": K + K * dim + dim * K * K + 2 * dim + 1,
            "adjoint": K * K, "eigenvectors": K + 2 * dim * K * K, "char_apply": 3 * K,
            "roe_average": 3 * K, "eos_pvt": K + 3, "viscous_flux": K + dim * dim + dim + K * dim}[op]
