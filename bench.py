@@ -356,9 +356,7 @@ def bench_serving(rates, count: int, warmup: int, slots: int = 8, batch_mb: floa
 def bench_batched(steps: int, warmup: int, dtype, nblocks: int = 512):
     """512 uneven 3D blocks (sizes log-uniform in [1e3, 1e6], 5 % near-vacuum
     points), fused pass: 512 stream launches, one 512-node HIP graph, and one
-    persistent graph-captured launch with a tuned configuration."""
-    import itertools
-
+    persistent graph-captured launch with the autotuned configuration."""
     import torch
     from paper_1809_09851_amd import batch as B
     from paper_1809_09851_amd import fdbb as F
@@ -394,21 +392,10 @@ def bench_batched(steps: int, warmup: int, dtype, nblocks: int = 512):
                                 "frac": round(nbytes / (ev * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     del g
     tasks = [B.fused_task(U, Fo, A, R, GAMMA) for U, Fo, A, R in blocks]
-    cus = torch.cuda.get_device_properties(0).multi_processor_count
-    best = None
-    for block, ppt, gmul, nt in itertools.product((64, 128, 256, 512), (1, 2, 4), (4, 8, 16), (0, 1)):
-        if block * ppt * 200 * (es // 4) // 2 > 160 * 1024:
-            continue
-        try:
-            plan = B.Plan(tasks, block=block, ppt=ppt, grid=cus * gmul, nontemporal=nt)
-        except F.FdbbError:
-            continue
-        _, ev = timed_launches(lambda: plan.run(graph=True), 3, 1)
-        if best is None or ev < best[0]:
-            best = (ev, (block, ppt, cus * gmul, nt))
-        plan.close()
-    block, ppt, grid, nt = best[1]
-    plan = B.Plan(tasks, block=block, ppt=ppt, grid=grid, nontemporal=nt)
+    # the autotuned batch configuration for this storage type (tune.py's
+    # batch entry, installed when the library loads)
+    plan = B.Plan(tasks)
+    block, ppt, grid, nt = plan.config()
     wall, ev = timed_launches(lambda: plan.run(graph=True), steps, warmup)
     res["persistent_graph"] = {"ms": round(ev, 4), "gpoints_s": round(points / ev / 1e6, 3),
                                "frac": round(nbytes / (ev * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

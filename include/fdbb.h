@@ -301,12 +301,16 @@ typedef struct fdbb_batch_plan fdbb_batch_plan;
  * into it.  Each task is validated as its single-call entry point would be.
  * The plan owns a device copy of the task table, the tile prefix sums and a
  * HIP graph holding one persistent kernel with `grid` workgroups of `block`
- * threads (64..256; grid 0 picks one sized to the device), `ppt` points per thread
- * and streaming (1: the nt bit) or regular (0) output stores.  Tasks that overlap
- * one another's outputs are rejected (FDBB_EALIAS).  Jacobian staging needs
- * LDS; a plan holds what its first task list needs, or, when created with
- * ntasks == 0, what any task needs (later task lists needing more than the
- * plan holds are rejected with FDBB_EINVAL).  Every op but
+ * threads (64..256 in multiples of 64; grid 0 picks one sized to the
+ * device), `ppt` points per thread (1, 2, 4 or 8) and regular (0),
+ * streaming (1: the nt bit) or streaming device-coherent (2: nt and sc1)
+ * output stores.  block == 0 takes the batch configuration installed for
+ * the first task's storage type (FDBB_F64 for an empty list; see
+ * fdbb_set_batch_config) and ignores ppt, grid and nontemporal.  Tasks that
+ * overlap one another's outputs are rejected (FDBB_EALIAS).  Jacobian
+ * staging needs LDS; a plan holds what its first task list needs, or, when
+ * created with ntasks == 0, what any task needs (later task lists needing
+ * more than the plan holds are rejected with FDBB_EINVAL).  Every op but
  * FDBB_OP_EIGENVECTORS, FDBB_OP_CHAR_APPLY, FDBB_OP_EOS_PVT and
  * FDBB_OP_VISCOUS_FLUX can be a task (FDBB_EINVAL otherwise). */
 int fdbb_batch_plan_create(const fdbb_task *tasks, int ntasks, int capacity, int block,
@@ -321,6 +325,21 @@ int fdbb_batch_plan_update(fdbb_batch_plan *plan, const fdbb_task *tasks, int nt
  * captured HIP graph, 0 launches the same kernel directly. */
 int fdbb_batch_exec(fdbb_batch_plan *plan, void *stream, int use_graph);
 
+/* The batch configuration that plans created with block == 0, the
+ * allocation-free batch entry point with block == 0 and the request server
+ * use, per storage type: block (64..256, multiple of 64), ppt (1, 2, 4, 8),
+ * grid_per_cu workgroups per compute unit (0: 2048 / block), store mode
+ * nontemporal (0, 1, 2 as for plans).  The binding installs the autotuned
+ * table's entry at load; until then 256 threads, 1 point per thread, the
+ * default grid and streaming stores.  FDBB_EINVAL for values out of range
+ * or a configuration whose 3D Jacobian staging would not fit in LDS. */
+int fdbb_set_batch_config(int dtype, int block, int ppt, int grid_per_cu, int nontemporal);
+int fdbb_get_batch_config(int dtype, int *block, int *ppt, int *grid_per_cu, int *nontemporal);
+
+/* The launch configuration a plan was created with (any may be NULL). */
+int fdbb_batch_plan_config(const fdbb_batch_plan *plan, int *block, int *ppt, int *grid,
+                           int *nontemporal);
+
 /* Total points and tiles of the current task list (either may be NULL). */
 int fdbb_batch_plan_info(const fdbb_batch_plan *plan, int64_t *points, int64_t *tiles);
 
@@ -334,9 +353,10 @@ int fdbb_batch_plan_destroy(fdbb_batch_plan *plan);
  * 0), without a plan.  Allocates nothing: the task table goes into a fixed
  * device array of the library, one per device (about 230 KB, held until the
  * process ends), with room for FDBB_NOALLOC_MAX_TASKS tasks; more tasks give
- * FDBB_EINVAL.  Tasks, block (64..256), ppt, grid (0 picks one sized to the
- * device) and nontemporal are validated as for a plan, with the same
- * statuses; each call uploads only its own table, nothing needs clearing.
+ * FDBB_EINVAL.  Tasks, block (64..256, or 0 for the installed batch
+ * configuration), ppt, grid (0 picks one sized to the device) and
+ * nontemporal are validated as for a plan, with the same statuses; each
+ * call uploads only its own table, nothing needs clearing.
  * The table is copied from the library's static host staging array, a copy
  * that HIP completes before returning (pageable host memory), so the call
  * waits for the work already queued on `stream`; it is therefore not for

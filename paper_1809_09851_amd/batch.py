@@ -103,25 +103,36 @@ def riemann_task(U, R, gamma=1.4):
 MAX_NOALLOC_TASKS = 1024  # FDBB_NOALLOC_MAX_TASKS
 
 
-def run_noalloc(tasks, block=256, ppt=1, grid=0, nontemporal=1, stream=None):
+def run_noalloc(tasks, block=0, ppt=1, grid=0, nontemporal=1, stream=None):
     """One persistent launch of ``tasks`` through the allocation-free entry
-    point (at most MAX_NOALLOC_TASKS tasks)."""
+    point (at most MAX_NOALLOC_TASKS tasks); ``block=0`` takes the installed
+    batch configuration, as for plans."""
     arr = (F.Task * max(1, len(tasks)))(*tasks)
     F.check(F.library().fdbb_batch_run_noalloc(arr, len(tasks), block, ppt, grid, nontemporal,
                                                F._stream(stream)))
 
 
 class Plan:
-    """Owner of one ``fdbb_batch_plan``."""
+    """Owner of one ``fdbb_batch_plan``.  ``block=0`` (the default) takes the
+    autotuned batch configuration installed for the first task's storage
+    type (``fdbb_set_batch_config``); an explicit block uses the given
+    ``ppt``, ``grid`` and ``nontemporal``."""
 
-    def __init__(self, tasks, capacity=None, block=256, ppt=1, grid=0, nontemporal=1):
+    def __init__(self, tasks, capacity=None, block=0, ppt=1, grid=0, nontemporal=1):
         lib = F.library()
         arr = (F.Task * max(1, len(tasks)))(*tasks)
         self.capacity = capacity or max(1, len(tasks))
         self._h = ctypes.c_void_p()
         F.check(lib.fdbb_batch_plan_create(arr, len(tasks), self.capacity, block, ppt, grid,
                                            nontemporal, ctypes.byref(self._h)))
-        self.block, self.ppt = block, ppt
+        self.block, self.ppt, self.grid, self.nontemporal = self.config()
+
+    def config(self):
+        """(block, ppt, grid, nontemporal) the plan launches with."""
+        b, p, g, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        F.check(F.library().fdbb_batch_plan_config(self._h, ctypes.byref(b), ctypes.byref(p), ctypes.byref(g),
+                                                   ctypes.byref(t)))
+        return b.value, p.value, g.value, t.value
 
     def update(self, tasks, stream=None):
         arr = (F.Task * max(1, len(tasks)))(*tasks)

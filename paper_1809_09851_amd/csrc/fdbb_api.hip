@@ -121,6 +121,42 @@ Config get_config(int op, int dim, int dtype)
     return unpack(g_cfg[op][dim - 1][dtype].load(std::memory_order_relaxed));
 }
 
+// Launch configuration of the persistent batch kernel, per storage type:
+// what plans created with block == 0 (and the request server's plans) use.
+// grid_per_cu 0 sizes the grid to 2048 / block workgroups per compute unit.
+struct BatchConfig {
+    int block;
+    int ppt;
+    int grid_per_cu;
+    int nt;  // 0 regular, 1 nt, 2 nt + sc1
+};
+
+std::atomic<uint64_t> g_batch_cfg[2] = {{0}, {0}};
+
+uint64_t pack_batch(const BatchConfig &c)
+{
+    return (uint64_t)(uint16_t)c.block | ((uint64_t)(uint8_t)c.ppt << 16) | ((uint64_t)(uint8_t)c.nt << 24) |
+           ((uint64_t)(uint32_t)c.grid_per_cu << 32);
+}
+
+BatchConfig get_batch_config(int dtype)
+{
+    const uint64_t v = g_batch_cfg[dtype == FDBB_F32 ? 1 : 0].load(std::memory_order_relaxed);
+    if (v == 0) return BatchConfig{256, 1, 0, 1};
+    BatchConfig c;
+    c.block = (int)(v & 0xffff);
+    c.ppt = (int)((v >> 16) & 0xff);
+    c.nt = (int)((v >> 24) & 0xff);
+    c.grid_per_cu = (int)(uint32_t)(v >> 32);
+    return c;
+}
+
+bool batch_config_ok(int block, int ppt, int nt)
+{
+    return block >= 64 && block <= kMaxBlockStaged && block % 64 == 0 &&
+           (ppt == 1 || ppt == 2 || ppt == 4 || ppt == 8) && nt >= 0 && nt <= 2;
+}
+
 bool config_ok(int block, int ppt, int grid_cap, int nt)
 {
     return block >= 64 && block <= 1024 && block % 64 == 0 && (ppt == 1 || ppt == 2 || ppt == 4) &&
@@ -809,6 +845,7 @@ struct fdbb_batch_plan {
     int block = 256;
     int ppt = 1;
     int grid = 0;
+    int nt = 1;
     size_t lds = 0;
     int64_t points = 0;
     int64_t tiles = 0;
@@ -961,9 +998,16 @@ int fdbb_batch_plan_create(const fdbb_task *tasks, int ntasks, int capacity, int
     if (!plan) return fail(FDBB_EINVAL, "plan must not be NULL");
     *plan = nullptr;
     if (capacity < 1 || capacity < ntasks) return fail(FDBB_EINVAL, "capacity must be >= max(1, ntasks)");
-    if (!config_ok(block, ppt, grid, nontemporal) || block > kMaxBlockStaged)
-        return fail(FDBB_EINVAL, "invalid launch configuration (batches take at most 256 threads per workgroup)");
     if (ntasks > 0 && !tasks) return fail(FDBB_EINVAL, "tasks must not be NULL");
+    int grid_per_cu = 0;
+    if (block == 0) {
+        // the installed configuration of the first task's storage type
+        const BatchConfig bc = get_batch_config(ntasks > 0 ? tasks[0].dtype : FDBB_F64);
+        block = bc.block, ppt = bc.ppt, nontemporal = bc.nt, grid_per_cu = bc.grid_per_cu, grid = 0;
+    }
+    if (!batch_config_ok(block, ppt, nontemporal) || grid < 0)
+        return fail(FDBB_EINVAL, "invalid launch configuration (batches take 64..256 threads per workgroup in "
+                                 "multiples of 64, 1, 2, 4 or 8 points per thread, store mode 0, 1 or 2)");
     // Argument checks of every task come before any HIP call.
     for (int b = 0; b < ntasks; ++b) {
         if (!batchable(tasks[b].op))
@@ -981,7 +1025,8 @@ int fdbb_batch_plan_create(const fdbb_task *tasks, int ntasks, int capacity, int
     p->capacity = capacity;
     p->block = block;
     p->ppt = ppt;
-    p->kernel = kernel_batch(ppt, nontemporal != 0);
+    p->kernel = kernel_batch(ppt, nontemporal);
+    p->nt = nontemporal;
     (void)hipGetDevice(&p->device);
     // LDS for the largest Jacobian staging among the first task list; a plan
     // created empty reserves enough for any task (3D FP64 blocks).
@@ -996,7 +1041,7 @@ int fdbb_batch_plan_create(const fdbb_task *tasks, int ntasks, int capacity, int
         free_plan(p);
         return rc;
     }
-    p->grid = grid > 0 ? grid : dev.cus * std::max(1, 2048 / block);
+    p->grid = grid > 0 ? grid : dev.cus * (grid_per_cu > 0 ? grid_per_cu : std::max(1, 2048 / block));
     p->bytes = table_bytes(capacity);
     hipError_t e = hipMalloc((void **)&p->dev, p->bytes);
     if (e != hipSuccess) {
@@ -1076,6 +1121,40 @@ int fdbb_batch_exec(fdbb_batch_plan *plan, void *stream, int use_graph)
     return launch_plan(plan, (hipStream_t)stream);
 }
 
+int fdbb_set_batch_config(int dtype, int block, int ppt, int grid_per_cu, int nontemporal)
+{
+    g_last_error.clear();
+    if (dtype != FDBB_F64 && dtype != FDBB_F32) return fail(FDBB_EINVAL, "unknown dtype");
+    if (!batch_config_ok(block, ppt, nontemporal) || grid_per_cu < 0 || grid_per_cu > 64)
+        return fail(FDBB_EINVAL, "invalid batch configuration");
+    // a plan of this configuration must be able to stage 3D Jacobian blocks
+    if (lds_bytes(FDBB_OP_FLUX_JACOBIAN, 3, dtype, block, ppt) > 160 * 1024)
+        return fail(FDBB_EINVAL, "batch configuration needs more LDS than a workgroup may use");
+    g_batch_cfg[dtype == FDBB_F32 ? 1 : 0].store(pack_batch(BatchConfig{block, ppt, grid_per_cu, nontemporal}));
+    return FDBB_OK;
+}
+
+int fdbb_get_batch_config(int dtype, int *block, int *ppt, int *grid_per_cu, int *nontemporal)
+{
+    if (dtype != FDBB_F64 && dtype != FDBB_F32) return fail(FDBB_EINVAL, "unknown dtype");
+    const BatchConfig c = get_batch_config(dtype);
+    if (block) *block = c.block;
+    if (ppt) *ppt = c.ppt;
+    if (grid_per_cu) *grid_per_cu = c.grid_per_cu;
+    if (nontemporal) *nontemporal = c.nt;
+    return FDBB_OK;
+}
+
+int fdbb_batch_plan_config(const fdbb_batch_plan *plan, int *block, int *ppt, int *grid, int *nontemporal)
+{
+    if (!plan) return fail(FDBB_EINVAL, "plan must not be NULL");
+    if (block) *block = plan->block;
+    if (ppt) *ppt = plan->ppt;
+    if (grid) *grid = plan->grid;
+    if (nontemporal) *nontemporal = plan->nt;
+    return FDBB_OK;
+}
+
 int fdbb_batch_plan_info(const fdbb_batch_plan *plan, int64_t *points, int64_t *tiles)
 {
     if (!plan) return fail(FDBB_EINVAL, "plan must not be NULL");
@@ -1097,9 +1176,15 @@ int fdbb_batch_run_noalloc(const fdbb_task *tasks, int ntasks, int block, int pp
     if (ntasks < 0 || ntasks > FDBB_NOALLOC_MAX_TASKS)
         return fail(FDBB_EINVAL, "the allocation-free batch takes 0 to " + std::to_string(FDBB_NOALLOC_MAX_TASKS) +
                                      " tasks, got " + std::to_string(ntasks));
-    if (!config_ok(block, ppt, grid, nontemporal) || block > kMaxBlockStaged)
-        return fail(FDBB_EINVAL, "invalid launch configuration (batches take at most 256 threads per workgroup)");
     if (ntasks > 0 && !tasks) return fail(FDBB_EINVAL, "tasks must not be NULL");
+    int grid_per_cu = 0;
+    if (block == 0) {
+        const BatchConfig bc = get_batch_config(ntasks > 0 ? tasks[0].dtype : FDBB_F64);
+        block = bc.block, ppt = bc.ppt, nontemporal = bc.nt, grid_per_cu = bc.grid_per_cu, grid = 0;
+    }
+    if (!batch_config_ok(block, ppt, nontemporal) || grid < 0)
+        return fail(FDBB_EINVAL, "invalid launch configuration (batches take 64..256 threads per workgroup in "
+                                 "multiples of 64, 1, 2, 4 or 8 points per thread, store mode 0, 1 or 2)");
     DeviceInfo dev;
     int rc = device_info(&dev);
     if (rc) return rc;
@@ -1117,7 +1202,7 @@ int fdbb_batch_run_noalloc(const fdbb_task *tasks, int ntasks, int block, int pp
     void *table = nullptr;
     const int se = batch_scratch(&table);
     if (se) return fail_hip((hipError_t)se, "hipGetSymbolAddress of the batch task table");
-    const void *kernel = kernel_batch(ppt, nontemporal != 0);
+    const void *kernel = kernel_batch(ppt, nontemporal);
     if (!kernel) return fail(FDBB_EINVAL, "no batch kernel for this configuration");
     if ((rc = set_lds_attr(kernel, info.lds, dev))) return rc;
     // From pageable host memory the copy completes before the call returns,
@@ -1131,7 +1216,7 @@ int fdbb_batch_run_noalloc(const fdbb_task *tasks, int ntasks, int block, int pp
     const int64_t *prefix = table_prefix(base);
     const int64_t *header = table_header(base);
     void *args[] = {&dtasks, &prefix, &header};
-    const int g = grid > 0 ? grid : dev.cus * std::max(1, 2048 / block);
+    const int g = grid > 0 ? grid : dev.cus * (grid_per_cu > 0 ? grid_per_cu : std::max(1, 2048 / block));
     e = hipLaunchKernel(kernel, dim3((unsigned)g), dim3((unsigned)block), args, info.lds, (hipStream_t)stream);
     if (e != hipSuccess) return fail_hip(e, "batch kernel launch");
     return FDBB_OK;

@@ -57,8 +57,9 @@ const void *kernel_eigen(int family, int dim, int dtype, int ppt, bool nt);
 
 // Persistent batch kernel: void k(const TaskDev*, const int64_t* prefix,
 // const int64_t* header).  header = {ntasks, ntiles}; prefix has ntasks + 1
-// entries, prefix[b] = first tile of task b.
-const void *kernel_batch(int ppt, bool nt);
+// entries, prefix[b] = first tile of task b.  ppt 1, 2, 4 or 8; store_mode
+// 0 regular, 1 nt, 2 nt + sc1.
+const void *kernel_batch(int ppt, int store_mode);
 
 // The allocation-free batch entry point's fixed task table: room for
 // kNoAllocMaxTasks tasks in the layout of a plan's table (header, tile

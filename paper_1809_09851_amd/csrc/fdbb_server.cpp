@@ -348,7 +348,7 @@ int fdbb_server_create(int64_t budget_bytes, int slots, int max_batch, double ma
             return FDBB_EHIP;
         }
         if (mode == FDBB_SERVE_BATCHED &&
-            (rc = fdbb_batch_plan_create(nullptr, 0, std::max(1, max_batch), 256, 1, 0, 1, &slot.plan))) {
+            (rc = fdbb_batch_plan_create(nullptr, 0, std::max(1, max_batch), 0, 0, 0, 0, &slot.plan))) {
             fdbb_server_destroy(s);
             return rc;
         }

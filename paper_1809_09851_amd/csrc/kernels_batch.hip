@@ -87,14 +87,25 @@ int batch_scratch(void **ptr)
     return 0;
 }
 
-const void *kernel_batch(int ppt, bool nt)
+template <int NT>
+static const void *pick_batch(int ppt)
 {
     switch (ppt) {
-    // streaming stores with nt alone: the persistent launch measured slower
-    // with nt + sc1 (1-7 %), unlike the single-launch fused kernel
-    case 1: return nt ? (const void *)&k_batch<1, kStoreNT> : (const void *)&k_batch<1, kStoreRegular>;
-    case 2: return nt ? (const void *)&k_batch<2, kStoreNT> : (const void *)&k_batch<2, kStoreRegular>;
-    case 4: return nt ? (const void *)&k_batch<4, kStoreNT> : (const void *)&k_batch<4, kStoreRegular>;
+    case 1: return (const void *)&k_batch<1, NT>;
+    case 2: return (const void *)&k_batch<2, NT>;
+    case 4: return (const void *)&k_batch<4, NT>;
+    case 8: return (const void *)&k_batch<8, NT>;
+    default: return nullptr;
+    }
+}
+
+// store_mode: 0 regular, 1 nt, 2 nt + sc1 (a batch plan's `nontemporal`).
+const void *kernel_batch(int ppt, int store_mode)
+{
+    switch (store_mode) {
+    case 0: return pick_batch<kStoreRegular>(ppt);
+    case 1: return pick_batch<kStoreNT>(ppt);
+    case 2: return pick_batch<kStoreNTSc1>(ppt);
     default: return nullptr;
     }
 }

@@ -110,6 +110,9 @@ def library():
         lib.fdbb_batch_exec.argtypes = [_p, _p, _i]
         lib.fdbb_batch_plan_info.argtypes = [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
         lib.fdbb_batch_plan_destroy.argtypes = [_p]
+        lib.fdbb_set_batch_config.argtypes = [_i, _i, _i, _i, _i]
+        lib.fdbb_get_batch_config.argtypes = [_i] + [ctypes.POINTER(_i)] * 4
+        lib.fdbb_batch_plan_config.argtypes = [_p] + [ctypes.POINTER(_i)] * 4
         lib.fdbb_batch_run_noalloc.argtypes = [ctypes.POINTER(Task), _i, _i, _i, _i, _i, _p]
         lib.fdbb_task_check.argtypes = [ctypes.POINTER(Task)]
         lib.fdbb_task_run.argtypes = [ctypes.POINTER(Task), _p]
@@ -376,6 +379,19 @@ def fdbb_get_launch_config(op, dim, dtype):
     b, p, g, t = _i(), _i(), _i(), _i()
     check(library().fdbb_get_launch_config(op, dim, dtype, ctypes.byref(b), ctypes.byref(p),
                                            ctypes.byref(g), ctypes.byref(t)))
+    return b.value, p.value, g.value, t.value
+
+
+def fdbb_set_batch_config(dtype, block, ppt, grid_per_cu=0, nontemporal=1):
+    check(library().fdbb_set_batch_config(dtype, block, ppt, grid_per_cu, nontemporal))
+
+
+def fdbb_get_batch_config(dtype):
+    """(block, ppt, grid_per_cu, nontemporal) that batch plans created with
+    block 0 use for storage type `dtype`."""
+    b, p, g, t = _i(), _i(), _i(), _i()
+    check(library().fdbb_get_batch_config(dtype, ctypes.byref(b), ctypes.byref(p), ctypes.byref(g),
+                                          ctypes.byref(t)))
     return b.value, p.value, g.value, t.value
 
 

@@ -226,14 +226,15 @@ class GpuBatchExecutor:
     """One batch plan and one stream per slot; a launch packs all of its
     requests into the plan's task table and replays the plan's graph."""
 
-    def __init__(self, slots: int, capacity: int = 256, block: int = 256, ppt: int = 1):
+    def __init__(self, slots: int, capacity: int = 256, block: int = 0, ppt: int = 1):
         import torch
 
         from . import batch as B
         self.torch = torch
         self.B = B
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
-        # empty plans reserve LDS for any task (3D FP64 Jacobian staging)
+        # empty plans reserve LDS for any task (3D FP64 Jacobian staging);
+        # block 0 takes the autotuned batch configuration
         self.plans = [B.Plan([], capacity=capacity, block=block, ppt=ppt) for _ in range(slots)]
         self.events = [None] * slots
 

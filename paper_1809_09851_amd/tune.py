@@ -9,6 +9,11 @@ binding applies the table shipped next to the library when it loads it.
 
     python -m paper_1809_09851_amd.tune --ops fused,flux_jacobian --dims 3 \\
         --dtypes f64,f32 --n 16777216 --write paper_1809_09851_amd/tuned_gfx950.json
+
+The op ``batch`` tunes the persistent batch kernel (block x points per
+thread x workgroups per compute unit x store mode) on the 512-block batched
+workload and stores it as ``batch/3/<dtype>``; plans created without an
+explicit configuration, and the request server, use it.
 """
 from __future__ import annotations
 
@@ -29,6 +34,12 @@ BLOCKS = (64, 128, 256, 512, 1024)
 PPTS = (1, 2, 4)
 GRID_CAPS = (0, 2048, 4096, 8192)
 STORE_MODES = (1, 0)
+# the persistent batch kernel: block x points per thread x workgroups per
+# compute unit x store mode (0 regular, 1 nt, 2 nt + sc1)
+BATCH_BLOCKS = (64, 128, 256)
+BATCH_PPTS = (1, 2, 4, 8)
+BATCH_GRID_PER_CU = (2, 4, 8, 16)
+BATCH_STORE_MODES = (1, 2, 0)
 DEFAULT_TABLE = os.environ.get(
     "FDBB_TUNED_TABLE", os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_gfx950.json"))
 DT = {"f64": (F.F64, torch.float64), "f32": (F.F32, torch.float32)}
@@ -182,6 +193,59 @@ def search(op: str, dim: int, dt: str, n: int, reps: int = 7, space=None, verbos
     return results
 
 
+def batch_workload(dtype, nblocks: int = 512, seed: int = 2):
+    """The batched workload: `nblocks` 3D blocks of sizes log-uniform in
+    [10^3, 10^6] points with 5 % near-vacuum points (seeded), each a fused
+    pass (flux, Jacobians, invariants) into its own outputs on the device.
+    Returns (tasks, points, the tensors the tasks point into)."""
+    from . import batch as B
+    from . import inputs
+    sizes, Vs = inputs.batched(3, nblocks, seed=seed)
+    keep, tasks = [], []
+    for V in Vs:
+        n = V.shape[1]
+        Vg = F.to_fields(torch.from_numpy(V).to(dtype).cuda())
+        U = F.empty_fields(5, n, dtype)
+        F.fdbb_prim2cons(3, GAMMA, Vg, U)
+        out = (F.empty_fields(15, n, dtype), F.empty_blocks(3, n, dtype), F.empty_fields(7, n, dtype))
+        tasks.append(B.fused_task(U, *out, gamma=GAMMA))
+        keep.append((U, out))
+        del Vg
+    torch.cuda.synchronize()
+    return tasks, int(sizes.sum()), keep
+
+
+def search_batch(dt: str, reps: int = 5, space=None, verbose=False, nblocks: int = 512):
+    """Time every batch configuration on the batched workload (one
+    persistent graph-captured launch each); returns [(ms, (block, ppt,
+    grid_per_cu, nt))] sorted and installs the fastest for `dt`."""
+    from . import batch as B
+    code, dtype = DT[dt]
+    es = 8 if dt == "f64" else 4
+    tasks, points, keep = batch_workload(dtype, nblocks)
+    cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    space = space or list(itertools.product(BATCH_BLOCKS, BATCH_PPTS, BATCH_GRID_PER_CU, BATCH_STORE_MODES))
+    results = []
+    for block, ppt, gpc, nt in space:
+        if block * ppt * 25 * es > 160 * 1024:  # 3D Jacobian staging must fit in LDS
+            continue
+        try:
+            plan = B.Plan(tasks, block=block, ppt=ppt, grid=cus * gpc, nontemporal=nt)
+        except F.FdbbError:
+            continue
+        ms = time_launch(lambda: plan.run(graph=True), reps)
+        plan.close()
+        results.append((ms, (block, ppt, gpc, nt)))
+        if verbose:
+            print(f"  batch {dt} cfg={(block, ppt, gpc, nt)} {ms:.4f} ms", file=sys.stderr, flush=True)
+    results.sort()
+    if results:
+        F.fdbb_set_batch_config(code, *results[0][1])
+    del keep, tasks
+    torch.cuda.empty_cache()
+    return results, points
+
+
 def load_table(path: str = DEFAULT_TABLE):
     try:
         with open(path) as f:
@@ -206,7 +270,10 @@ def apply_table(path: str = DEFAULT_TABLE, key: str | None = None) -> int:
         op, dim, dt = name.split("/")
         code = DT[dt][0]
         try:
-            F.fdbb_set_launch_config(op, int(dim), code, e["block"], e["ppt"], e["grid_cap"], e["nt"])
+            if op == "batch":
+                F.fdbb_set_batch_config(code, e["block"], e["ppt"], e["grid_per_cu"], e["nt"])
+            else:
+                F.fdbb_set_launch_config(op, int(dim), code, e["block"], e["ppt"], e["grid_cap"], e["nt"])
         except F.FdbbError as exc:  # an entry the library no longer accepts keeps the default
             print(f"fdbb: ignoring tuned entry {name}: {exc}", file=sys.stderr)
             continue
@@ -230,6 +297,20 @@ def main(argv=None):
     table = (load_table(args.write) if args.write else None) or {}
     entries = table.setdefault(key, {})
     for op in args.ops.split(","):
+        if op == "batch":
+            # the batched workload is 3D whatever --dims says
+            for dt in args.dtypes.split(","):
+                res, points = search_batch(dt, max(3, args.reps - 2), verbose=args.verbose)
+                if not res:
+                    continue
+                best_ms, (block, ppt, gpc, nt) = res[0]
+                base = [ms for ms, cfg in res if cfg == (256, 1, 8, 1)]
+                entries[f"batch/3/{dt}"] = {"block": block, "ppt": ppt, "grid_per_cu": gpc, "nt": nt,
+                                            "ms": round(best_ms, 5), "n": points,
+                                            "default_ms": round(base[0], 5) if base else None,
+                                            "top5": [[round(ms, 5), list(c)] for ms, c in res[:5]]}
+                print(json.dumps({f"batch/3/{dt}": entries[f"batch/3/{dt}"]}), flush=True)
+            continue
         for dim in (int(d) for d in args.dims.split(",")):
             for dt in args.dtypes.split(","):
                 n = (auto_size(op, dim, 8 if dt == "f64" else 4) if args.n == "auto" else int(args.n))

@@ -129,6 +129,26 @@ def test_noalloc_batch_rejects_before_any_hip_call():
     assert lib.fdbb_batch_run_noalloc(None, 2, 256, 1, 0, 1, None) == F.EINVAL
 
 
+def test_batch_config_table():
+    lib = F.library()
+    old = F.fdbb_get_batch_config(F.F64)
+    try:
+        assert lib.fdbb_set_batch_config(F.F64, 128, 4, 8, 2) == F.OK
+        assert F.fdbb_get_batch_config(F.F64) == (128, 4, 8, 2)
+        # out of range, or 3D FP64 Jacobian staging beyond the LDS
+        assert lib.fdbb_set_batch_config(F.F64, 320, 1, 0, 1) == F.EINVAL
+        assert lib.fdbb_set_batch_config(F.F64, 96, 1, 0, 1) == F.EINVAL
+        assert lib.fdbb_set_batch_config(F.F64, 64, 3, 0, 1) == F.EINVAL
+        assert lib.fdbb_set_batch_config(F.F64, 64, 1, 0, 3) == F.EINVAL
+        assert lib.fdbb_set_batch_config(F.F64, 64, 1, -1, 1) == F.EINVAL
+        assert lib.fdbb_set_batch_config(F.F64, 256, 4, 0, 1) == F.EINVAL
+        assert lib.fdbb_set_batch_config(F.F32, 256, 4, 0, 1) == F.OK  # half the bytes fit
+        assert lib.fdbb_set_batch_config(5, 64, 1, 0, 1) == F.EINVAL
+        assert F.fdbb_get_batch_config(F.F64) == (128, 4, 8, 2)
+    finally:
+        F.fdbb_set_batch_config(F.F64, *old)
+
+
 def test_eigen_and_char_apply_checks():
     lib = F.library()
     assert lib.fdbb_eigenvectors(3, 1.4, 0, A0, 128, None, 0, None, 0, 100, None) == F.EINVAL

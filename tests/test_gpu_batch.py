@@ -197,3 +197,27 @@ def test_overlapping_tasks_are_rejected():
     with pytest.raises(F.FdbbError) as e:
         B.Plan([t1, t2])
     assert e.value.status == F.EALIAS
+
+
+def test_plans_take_the_installed_batch_configuration():
+    """block 0 takes what fdbb_set_batch_config installed for the first
+    task's storage type; an explicit configuration is kept as given."""
+    _, U = states(3, 5000, 91, "f32")
+    out = (F.empty_fields(15, 5000, U.dtype), F.empty_blocks(3, 5000, U.dtype), F.empty_fields(7, 5000, U.dtype))
+    t = [B.fused_task(U, *out, gamma=GAMMA)]
+    old = F.fdbb_get_batch_config(F.F32)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    try:
+        F.fdbb_set_batch_config(F.F32, 64, 8, 4, 2)
+        p = B.Plan(t)
+        assert p.config() == (64, 8, 4 * cus, 2)
+        p.run(graph=True)
+        torch.cuda.synchronize()
+        Fo, Ao, Ro = F.euler_fused(U, GAMMA)
+        assert blocks_error(host(out[1]), host(Ao)) <= 1.2e-7
+        p.close()
+        q = B.Plan(t, block=128, ppt=2, grid=77, nontemporal=0)
+        assert q.config() == (128, 2, 77, 0)
+        q.close()
+    finally:
+        F.fdbb_set_batch_config(F.F32, *old)
