@@ -216,6 +216,29 @@ def bench_fused(n: int, steps: int, warmup: int, dtype, label: str):
     return out
 
 
+def bench_reallocations(n: int, count: int, steps: int = 5, warmup: int = 2):
+    """The fused 3D FP64 pass on `count` fresh sets of buffers (inputs and
+    outputs allocated anew each time, the allocator's cache emptied first):
+    mean HIP-event ms per launch for each allocation.  On this device the
+    pass's time depends on the allocation it runs in."""
+    import torch
+    from paper_1809_09851_amd import fdbb as F
+    V = device_state(3, n, 1, torch.float64)
+    out = []
+    for _ in range(count):
+        torch.cuda.empty_cache()
+        U = F.empty_fields(5, n, torch.float64)
+        U.copy_(V)
+        Fo, A, R = F.empty_fields(15, n), F.empty_blocks(3, n), F.empty_fields(7, n)
+        _, ev = timed_launches(lambda: F.fdbb_euler_fused(3, GAMMA, U, Fo, A, R), steps, warmup)
+        out.append(round(ev, 4))
+        print(f"# fused 3D f64 on allocation {len(out)}: {ev:.4f} ms", file=sys.stderr, flush=True)
+        del U, Fo, A, R
+    del V
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_separate(n: int, steps: int, warmup: int, dtype):
     """The plain form: flux, Jacobian and invariants as three launches."""
     import torch
@@ -266,6 +289,45 @@ def bench_1d(steps: int, warmup: int):
         wall, ev = timed_launches(step, max(steps, sets), warmup)
         res[name] = {"gpoints_s": round(n / (ev * 1e-3) / 1e9, 3),
                      "achieved_gbs": round(bpp * n / (ev * 1e-3) / 1e9, 1)}
+    # the three ops of one step (136 B/pt together) as three launches, as a
+    # HIP graph of the three launches, and as one persistent batch launch
+    from paper_1809_09851_amd import batch as B
+    ctr = [0]
+
+    def three():
+        k = ctr[0] % sets
+        ctr[0] += 1
+        F.fdbb_cons2prim(1, GAMMA, Us[k], Vs[k])
+        F.fdbb_eos(1, GAMMA, Us[k], ps[k], cs[k])
+        F.fdbb_flux(1, GAMMA, Us[k], Fs[k])
+
+    graphs = []
+    for k in range(sets):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            F.fdbb_cons2prim(1, GAMMA, Us[k], Vs[k])
+            F.fdbb_eos(1, GAMMA, Us[k], ps[k], cs[k])
+            F.fdbb_flux(1, GAMMA, Us[k], Fs[k])
+        graphs.append(g)
+    plans = [B.Plan([B.cons2prim_task(Us[k], Vs[k], GAMMA), B.eos_task(Us[k], ps[k], cs[k], GAMMA),
+                     B.flux_task(Us[k], Fs[k], GAMMA)]) for k in range(sets)]
+
+    def rotate(fns):
+        c = [0]
+
+        def step():
+            fns[c[0] % sets]()
+            c[0] += 1
+        return step
+
+    for name, step in (("three_launches", three), ("graph_of_three", rotate([g.replay for g in graphs])),
+                       ("one_persistent_launch", rotate([(lambda p=p: p.run(graph=True)) for p in plans]))):
+        wall, ev = timed_launches(step, max(steps, sets), warmup)
+        res[name] = {"us_per_step": round(ev * 1e3, 2), "gpoints_s": round(n / (ev * 1e-3) / 1e9, 3),
+                     "achieved_gbs": round(136 * n / (ev * 1e-3) / 1e9, 1)}
+    for p in plans:
+        p.close()
+    del graphs, plans
     del Us, Vs, Fs, ps, cs
     torch.cuda.empty_cache()
     return res
@@ -442,7 +504,7 @@ def bench_ops(steps: int, warmup: int, dims=(3,), dtypes=("f64", "f32")):
     import torch
     from paper_1809_09851_amd import tune
     out = {}
-    ops = ("cons2prim", "prim2cons", "eos", "v_mag2", "flux", "flux_jacobian", "riemann_invariants",
+    ops = ("cons2prim", "prim2cons", "eos", "v_mag2", "flux", "flux_dir", "flux_jacobian", "riemann_invariants",
            "cons2char", "char2cons", "adjoint", "eigenvectors", "char_apply", "roe_average", "eos_pvt",
            "viscous_flux")
     for dim in dims:
@@ -520,6 +582,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=1 << 24)
     ap.add_argument("--extras", action="store_true", help="also time the other building blocks")
+    ap.add_argument("--reallocs", type=int, default=6,
+                    help="also time the fused pass on this many fresh buffer allocations (0 skips)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--serve-rates", default="100,300,1000,3000,10000",
                     help="comma-separated Poisson rates (req/s) for the serving measurement; '' skips it")
@@ -583,6 +647,12 @@ def main(argv=None):
     ceiling = write_ceiling()
     line["roofline"]["measured_write_ceiling_gbs"] = round(ceiling, 1)
     line["roofline"]["frac_of_measured_ceiling"] = round(achieved / ceiling, 4)
+    if args.reallocs > 0:
+        ms = bench_reallocations(args.n, args.reallocs)
+        nbytes = fused_bytes(3, 8) * args.n
+        line["allocation_spread"] = {
+            "what": "the same pass on freshly allocated buffers, one entry per allocation",
+            "kernel_ms": ms, "frac": [round(nbytes / (m * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) for m in ms]}
     if args.extras:
         ex = {}
         f32 = bench_fused(args.n, args.steps, args.warmup, torch.float32, "3d_f32_fused")

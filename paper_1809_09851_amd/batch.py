@@ -66,6 +66,15 @@ def jacobian_task(U, A, gamma=1.4):
     return t
 
 
+def eos_task(U, p=None, c=None, gamma=1.4):
+    dim = U.shape[0] - 2
+    t = _task("eos", dim, F.dtype_code(U.dtype), gamma, U.shape[1])
+    _set(t, "in0", U, dim + 2)
+    _set(t, "out0", p)
+    _set(t, "out1", c)
+    return t
+
+
 def cons2prim_task(U, V, gamma=1.4):
     dim = U.shape[0] - 2
     t = _task("cons2prim", dim, F.dtype_code(U.dtype), gamma, U.shape[1])
