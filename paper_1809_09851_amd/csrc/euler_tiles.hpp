@@ -93,8 +93,8 @@ __device__ __forceinline__ void load_chunk(const T *__restrict__ p, int cnt, boo
 // The single-launch kernels that write K x K blocks (fused pass, flux
 // Jacobian, eigenvector blocks) stream with nt + sc1, under which they ran
 // 1.8-3.5 % faster on this device than with nt alone (a plain write
-// stream: 7.0 against 6.7-6.8 TB/s); the persistent batch kernel streams
-// with nt, which measured faster for it.
+// stream: 7.0 against 6.7-6.8 TB/s).  The persistent batch kernel takes any
+// of the three modes; its autotuned configuration picks one.
 enum : int { kStoreRegular = 0, kStoreNT = 1, kStoreNTSc1 = 2 };
 
 // No compiler builtin sets sc1 on a global store, hence the inline
