@@ -43,12 +43,15 @@ struct Args {
 template <typename T, int N>
 using vec_t = T __attribute__((ext_vector_type(N)));
 
-// Points per chunk (at most two: 16 bytes of FP64, 8 of FP32) and chunks
-// per thread.  A chunk is the unit of one vector access and of the FP64
-// per-point state held in registers at one time.
+// Points per chunk and chunks per thread.  A chunk is the unit of one
+// vector access and of the FP64 per-point state held in registers at one
+// time: up to 16 bytes, two FP64 or four FP32 values, when the thread has
+// that many points (two points, 8 bytes, for FP32 at two points per
+// thread).
 template <typename T, int P>
 struct Chunk {
-    static constexpr int W = P >= 2 ? 2 : 1;
+    static constexpr int VW = 16 / (int)sizeof(T);
+    static constexpr int W = P >= VW ? VW : (P >= 2 ? 2 : 1);
     static constexpr int N = P / W;
 };
 
