@@ -368,9 +368,23 @@ def bench_autograd(steps: int, warmup: int):
         (euler_flux(U, GAMMA) * w).sum().backward()
 
     wall, ev = timed_launches(step, steps, warmup)
-    del U, w
+    # the library's share: the flux kernel of the forward pass and the
+    # adjoint kernel of the backward pass (the loss's product, sum and
+    # broadcast gradient are PyTorch's own kernels)
+    Ud = U.detach()
+    Fo = F.empty_fields(15, n, torch.float64)
+    Ub = F.empty_fields(5, n, torch.float64)
+
+    def kernels():
+        F.fdbb_flux(dim, GAMMA, Ud, Fo)
+        F.fdbb_flux_adjoint(dim, -1, GAMMA, Ud, w, Ub)
+
+    _, ev_k = timed_launches(kernels, steps, warmup)
+    del U, w, Ud, Fo, Ub
     torch.cuda.empty_cache()
-    return {"n": n, "ms_per_fwd_bwd": round(wall, 4), "gpoints_s": round(n / (wall * 1e-3) / 1e9, 3)}
+    return {"n": n, "ms_per_fwd_bwd": round(wall, 4), "gpoints_s": round(n / (wall * 1e-3) / 1e9, 3),
+            "flux_and_adjoint_kernels_ms": round(ev_k, 4),
+            "kernel_gbs": round(360 * n / (ev_k * 1e-3) / 1e9, 1)}
 
 
 def bench_serving(rates, count: int, warmup: int, slots: int = 8, batch_mb: float = 64.0,
