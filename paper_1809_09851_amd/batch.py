@@ -58,6 +58,15 @@ def flux_task(U, F_, gamma=1.4):
     return t
 
 
+def flux_dir_task(U, Fd, direction, gamma=1.4):
+    """F_direction alone (K fields) of the state U."""
+    dim = U.shape[0] - 2
+    t = _task("flux_dir", dim, F.dtype_code(U.dtype), gamma, U.shape[1], direction)
+    _set(t, "in0", U, dim + 2)
+    _set(t, "out0", Fd, dim + 2)
+    return t
+
+
 def jacobian_task(U, A, gamma=1.4):
     dim = U.shape[0] - 2
     t = _task("flux_jacobian", dim, F.dtype_code(U.dtype), gamma, U.shape[1])

@@ -60,7 +60,8 @@ bool out_shape(const fdbb_task &t, OutShape *s)
     case FDBB_OP_CONS2CHAR:
     case FDBB_OP_CHAR2CONS:
     case FDBB_OP_ADJOINT:
-    case FDBB_OP_ROE_AVERAGE: s->bytes[0] = (size_t)(K * ld) * es; return true;
+    case FDBB_OP_ROE_AVERAGE:
+    case FDBB_OP_FLUX_DIR: s->bytes[0] = (size_t)(K * ld) * es; return true;
     case FDBB_OP_FLUX: s->bytes[0] = (size_t)(K * D * ld) * es; return true;
     case FDBB_OP_RIEMANN: s->bytes[0] = (size_t)((2 * D + 1) * ld) * es; return true;
     case FDBB_OP_FLUX_JACOBIAN: s->bytes[0] = (size_t)(D * ld * K * K) * es; return true;
@@ -87,7 +88,8 @@ double moved_bytes(const fdbb_task &t)
     case FDBB_OP_CONS2PRIM:
     case FDBB_OP_PRIM2CONS:
     case FDBB_OP_CONS2CHAR:
-    case FDBB_OP_CHAR2CONS: per = 2 * K; break;
+    case FDBB_OP_CHAR2CONS:
+    case FDBB_OP_FLUX_DIR: per = 2 * K; break;
     case FDBB_OP_ADJOINT: per = K * K; break;
     case FDBB_OP_ROE_AVERAGE: per = 3 * K; break;
     case FDBB_OP_FLUX: per = K + K * D; break;

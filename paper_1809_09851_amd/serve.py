@@ -30,7 +30,7 @@ OPS = ("cons2prim", "flux", "flux_jacobian", "adjoint")
 
 def out_shape(op: str, dim: int, n: int):
     K = dim + 2
-    if op == "cons2prim":
+    if op in ("cons2prim", "flux_dir"):
         return ("fields", K)
     if op == "flux":
         return ("fields", K * dim)
@@ -43,7 +43,7 @@ def out_shape(op: str, dim: int, n: int):
 
 def out_bytes(op: str, dim: int, n: int, elem: int) -> int:
     K = dim + 2
-    per_pt = {"cons2prim": K, "flux": K * dim, "flux_jacobian": dim * K * K, "adjoint": K}[op]
+    per_pt = {"cons2prim": K, "flux": K * dim, "flux_jacobian": dim * K * K, "adjoint": K, "flux_dir": K}[op]
     return per_pt * n * elem
 
 
@@ -51,7 +51,7 @@ def moved_bytes(op: str, dim: int, n: int, elem: int) -> int:
     """Algorithmic HBM bytes of one request (inputs read + outputs written)."""
     K = dim + 2
     per_pt = {"cons2prim": 2 * K, "flux": K + K * dim, "flux_jacobian": K + dim * K * K,
-              "adjoint": K + K * dim + K}[op]
+              "adjoint": K + K * dim + K, "flux_dir": 2 * K}[op]
     return per_pt * n * elem
 
 
@@ -495,7 +495,7 @@ def completion_outputs(c, op: str, dim: int, n: int, elem: int):
     def single(ptr):
         return torch.as_tensor(_DeviceArray(ptr, (ld,), elem), device="cuda")[:n]
 
-    if op in ("cons2prim", "prim2cons", "cons2char", "char2cons", "adjoint", "roe_average"):
+    if op in ("cons2prim", "prim2cons", "cons2char", "char2cons", "adjoint", "roe_average", "flux_dir"):
         return (fields(c.out0, K),)
     if op == "flux":
         return (fields(c.out0, K * dim),)

@@ -221,3 +221,24 @@ def test_plans_take_the_installed_batch_configuration():
         q.close()
     finally:
         F.fdbb_set_batch_config(F.F32, *old)
+
+
+@pytest.mark.parametrize("dt", ("f64", "f32"))
+def test_flux_direction_tasks_in_a_plan(dt):
+    """Per-direction flux tasks of every dim and direction in one persistent
+    launch equal the single-call kernel and the oracle's flux column."""
+    tasks, outs = [], []
+    for dim in (1, 2, 3):
+        for d in range(dim):
+            Uo, Ug = states(dim, 3001 + 97 * d + dim, 70 + 10 * dim + d, dt)
+            Fd = F.empty_fields(dim + 2, Ug.shape[1], Ug.dtype)
+            tasks.append(B.flux_dir_task(Ug, Fd, d, GAMMA))
+            outs.append((dim, d, Uo, Ug, Fd))
+    plan = B.Plan(tasks)
+    plan.run(graph=True)
+    torch.cuda.synchronize()
+    for dim, d, Uo, Ug, Fd in outs:
+        g = list(range(dim + 2))
+        assert group_error(host(Fd), oracle.flux(dim, GAMMA, Uo)[d::dim], [g]) <= TOL[dt]
+        assert group_error(host(Fd), host(F.flux(Ug, GAMMA, direction=d)), [g]) <= TOL[dt]
+    plan.close()

@@ -193,3 +193,29 @@ def test_zero_copy_outputs_match_copies(pools):
         assert ((a - b).abs().max() / den).item() <= tol
     srv.release(99)
     srv.close()
+
+
+def test_per_direction_flux_requests(pools):
+    """The server runs per-direction flux requests (K output fields) like
+    the single-call entry point."""
+    srv = S.NativeServer(8 * 10 ** 9, slots=2, max_batch=8, max_batch_bytes=1e12)
+    reqs = []
+    from paper_1809_09851_amd import batch as B
+    for k, (dim, d, elem) in enumerate([(3, 2, 8), (2, 0, 4), (1, 0, 8), (3, 1, 4)]):
+        U = pools.U[(dim, elem)][:, 64 * k: 64 * k + 20000 + 13 * k]
+        srv.submit(B.flux_dir_task(U, None, d, GAMMA), k)
+        reqs.append((dim, d, elem, U))
+    got = {}
+    t_end = time.time() + 60
+    while len(got) < len(reqs):
+        for c in srv.poll():
+            assert c.status == 0
+            dim, d, elem, U = reqs[c.tag]
+            (view,) = S.completion_outputs(c, "flux_dir", dim, U.shape[1], elem)
+            ref = F.flux(U, GAMMA, direction=d)
+            assert device_group_error(view, ref, [list(range(dim + 2))]) <= TOL["f64" if elem == 8 else "f32"]
+            got[c.tag] = True
+            srv.release(c.tag)
+        assert time.time() < t_end
+    assert srv.stats()["arena_bytes"] == 0
+    srv.close()
