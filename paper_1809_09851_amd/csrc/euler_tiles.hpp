@@ -109,13 +109,19 @@ enum : int { kStoreRegular = 0, kStoreNT = 1, kStoreNTSc1 = 2 };
 // arithmetic across them; that is safe because no kernel reads back what it
 // stores except an in-place transform, where each address is read and
 // written by one thread and the stored value depends on the loaded one.
+// A store of more than 64 bits reads its data registers during the two
+// wait states after it issues, and a VALU instruction that overwrites
+// them inside that window corrupts the stored value.  The compiler pads
+// its own wide stores for this, but it cannot see the store inside an asm
+// statement and reuses the registers as soon as the statement ends, so
+// the 16-byte form carries its own s_nop 1 (two wait states).
 template <int NT, typename V>
 __device__ __forceinline__ void put(V *p, V v)
 {
     if constexpr (NT == kStoreNTSc1) {
         static_assert(sizeof(V) == 4 || sizeof(V) == 8 || sizeof(V) == 16, "4-, 8- or 16-byte stores");
         if constexpr (sizeof(V) == 16)
-            asm volatile("global_store_dwordx4 %0, %1, off nt sc1" : : "v"(p), "v"(v));
+            asm volatile("global_store_dwordx4 %0, %1, off nt sc1\n\ts_nop 1" : : "v"(p), "v"(v));
         else if constexpr (sizeof(V) == 8)
             asm volatile("global_store_dwordx2 %0, %1, off nt sc1" : : "v"(p), "v"(v));
         else
