@@ -117,6 +117,25 @@ def timed_launches(fn, steps: int, warmup: int):
     return wall, ev
 
 
+def queued_launches(fn, launches: int):
+    """Mean HIP-event milliseconds per launch of `launches` back-to-back
+    calls of fn() (one event pair around all of them, after one warm-up
+    pass): the device's rate when the host keeps the stream fed."""
+    import torch
+    for _ in range(launches):
+        fn()
+    stream = torch.cuda.current_stream()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(launches):
+        fn()
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b) / launches
+
+
 def device_state(dim: int, n: int, seed: int, dtype):
     """Seeded primitive state -> GPU -> conservative state via the library."""
     import torch
@@ -263,7 +282,10 @@ def bench_separate(n: int, steps: int, warmup: int, dtype):
 
 def bench_1d(steps: int, warmup: int):
     """1D ops at N = 2^20, FP64; 32 rotating buffer sets so that the working
-    set (~1.6 GB) exceeds the 256 MB last-level cache."""
+    set (~1.6 GB) exceeds the 256 MB last-level cache.  Each op is timed one
+    launch per event pair (what a single call costs, launch latency
+    included) and as back-to-back launches (`queued_*`: the device's rate
+    while the host keeps the stream fed)."""
     import torch
     from paper_1809_09851_amd import fdbb as F
     n = 1 << 20
@@ -287,8 +309,11 @@ def bench_1d(steps: int, warmup: int):
             ctr[0] += 1
 
         wall, ev = timed_launches(step, max(steps, sets), warmup)
+        q = queued_launches(step, 8 * sets)
         res[name] = {"gpoints_s": round(n / (ev * 1e-3) / 1e9, 3),
-                     "achieved_gbs": round(bpp * n / (ev * 1e-3) / 1e9, 1)}
+                     "achieved_gbs": round(bpp * n / (ev * 1e-3) / 1e9, 1),
+                     "queued_us": round(q * 1e3, 2), "queued_gbs": round(bpp * n / (q * 1e-3) / 1e9, 1),
+                     "config": list(F.fdbb_launch_config_for(name, 1, F.F64, n))}
     # the three ops of one step (136 B/pt together) as three launches, as a
     # HIP graph of the three launches, and as one persistent batch launch
     from paper_1809_09851_amd import batch as B

@@ -252,6 +252,23 @@ int fdbb_set_launch_config(int op, int dim, int dtype, int block, int ppt, int g
 int fdbb_get_launch_config(int op, int dim, int dtype, int *block, int *ppt, int *grid_cap,
                            int *nontemporal);
 
+/* A second configuration per (op, dim, dtype) for small launches: a call of
+ * n <= max_n points uses it instead of the one above (a grid of few tiles
+ * pays its ramp-up and tail on every launch, so a different shape can win
+ * there).  The values are validated as above; max_n = 0 removes the entry
+ * (the other arguments are then not checked) and a negative max_n gives
+ * FDBB_EINVAL.  Process-wide, safe to update while other threads launch: a
+ * launch racing an update takes either the old or the new entry. */
+int fdbb_set_small_launch_config(int op, int dim, int dtype, int64_t max_n, int block, int ppt,
+                                 int grid_cap, int nontemporal);
+/* max_n 0 and the large configuration's values when no entry is set. */
+int fdbb_get_small_launch_config(int op, int dim, int dtype, int64_t *max_n, int *block, int *ppt,
+                                 int *grid_cap, int *nontemporal);
+/* The configuration a call of n points of (op, dim, dtype) launches with
+ * (outputs may be NULL); n < 0 gives FDBB_EINVAL. */
+int fdbb_launch_config_for(int op, int dim, int dtype, int64_t n, int *block, int *ppt, int *grid_cap,
+                           int *nontemporal);
+
 /* Resources of the kernel that (op, dim, dtype, ppt, nontemporal) launches:
  * vector registers per thread and private (spill) bytes per thread, which
  * cost memory traffic when non-zero.  Either output may be NULL.  Queries

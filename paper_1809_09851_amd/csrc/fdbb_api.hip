@@ -121,6 +121,21 @@ Config get_config(int op, int dim, int dtype)
     return unpack(g_cfg[op][dim - 1][dtype].load(std::memory_order_relaxed));
 }
 
+// The small-launch entries: calls of n <= g_small_max points take
+// g_small_cfg (no entry while g_small_max is 0).  The setter stores the
+// configuration before the bound and the remover clears the bound first, so
+// a launch that sees a non-zero bound also sees a configuration that was
+// valid for this (op, dim, dtype).
+std::atomic<uint64_t> g_small_cfg[FDBB_NUM_OPS][3][2];
+std::atomic<int64_t> g_small_max[FDBB_NUM_OPS][3][2];
+
+Config get_config(int op, int dim, int dtype, int64_t n)
+{
+    const int64_t max_n = g_small_max[op][dim - 1][dtype].load(std::memory_order_acquire);
+    if (max_n > 0 && n <= max_n) return unpack(g_small_cfg[op][dim - 1][dtype].load(std::memory_order_relaxed));
+    return get_config(op, dim, dtype);
+}
+
 // Launch configuration of the persistent batch kernel, per storage type:
 // what plans created with block == 0 (and the request server's plans) use.
 // grid_per_cu 0 sizes the grid to 2048 / block workgroups per compute unit.
@@ -370,7 +385,7 @@ int launch(Call &c, void *stream)
     if (rc) return rc;
     if (vector_ok(c)) c.a.flags |= kFlagVector;
 
-    const Config cfg = get_config(c.op, c.dim, c.dtype);
+    const Config cfg = get_config(c.op, c.dim, c.dtype, c.a.n);
     const void *fn = kernel_for(c.op, c.dim, c.dtype, cfg.ppt, cfg.nt != 0);
     if (!fn) return fail(FDBB_EINVAL, "no kernel for this configuration");
     DeviceInfo dev;
@@ -793,6 +808,56 @@ int fdbb_get_launch_config(int op, int dim, int dtype, int *block, int *ppt, int
     return FDBB_OK;
 }
 
+int fdbb_set_small_launch_config(int op, int dim, int dtype, int64_t max_n, int block, int ppt, int grid_cap,
+                                 int nontemporal)
+{
+    if (op < 0 || op >= FDBB_NUM_OPS || dim < 1 || dim > 3 || (dtype != FDBB_F64 && dtype != FDBB_F32))
+        return fail(FDBB_EINVAL, "unknown op, dim or dtype");
+    if (max_n < 0) return fail(FDBB_EINVAL, "max_n must not be negative");
+    if (max_n == 0) {
+        g_small_max[op][dim - 1][dtype].store(0, std::memory_order_release);
+        return FDBB_OK;
+    }
+    if (!config_ok(block, ppt, grid_cap, nontemporal)) return fail(FDBB_EINVAL, "invalid launch configuration");
+    if (stages_blocks(op) && block > kMaxBlockStaged)
+        return fail(FDBB_EINVAL, "kernels that stage K x K blocks take at most 256 threads per workgroup");
+    // clear the bound while the configuration changes, then publish both
+    g_small_max[op][dim - 1][dtype].store(0, std::memory_order_release);
+    g_small_cfg[op][dim - 1][dtype].store(pack(Config{block, ppt, grid_cap, nontemporal}), std::memory_order_relaxed);
+    g_small_max[op][dim - 1][dtype].store(max_n, std::memory_order_release);
+    return FDBB_OK;
+}
+
+int fdbb_get_small_launch_config(int op, int dim, int dtype, int64_t *max_n, int *block, int *ppt, int *grid_cap,
+                                 int *nontemporal)
+{
+    if (op < 0 || op >= FDBB_NUM_OPS || dim < 1 || dim > 3 || (dtype != FDBB_F64 && dtype != FDBB_F32))
+        return fail(FDBB_EINVAL, "unknown op, dim or dtype");
+    const int64_t m = g_small_max[op][dim - 1][dtype].load(std::memory_order_acquire);
+    const Config c = m > 0 ? unpack(g_small_cfg[op][dim - 1][dtype].load(std::memory_order_relaxed))
+                           : get_config(op, dim, dtype);
+    if (max_n) *max_n = m;
+    if (block) *block = c.block;
+    if (ppt) *ppt = c.ppt;
+    if (grid_cap) *grid_cap = c.grid_cap;
+    if (nontemporal) *nontemporal = c.nt;
+    return FDBB_OK;
+}
+
+int fdbb_launch_config_for(int op, int dim, int dtype, int64_t n, int *block, int *ppt, int *grid_cap,
+                           int *nontemporal)
+{
+    if (op < 0 || op >= FDBB_NUM_OPS || dim < 1 || dim > 3 || (dtype != FDBB_F64 && dtype != FDBB_F32))
+        return fail(FDBB_EINVAL, "unknown op, dim or dtype");
+    if (n < 0) return fail(FDBB_EINVAL, "n must not be negative");
+    const Config c = get_config(op, dim, dtype, n);
+    if (block) *block = c.block;
+    if (ppt) *ppt = c.ppt;
+    if (grid_cap) *grid_cap = c.grid_cap;
+    if (nontemporal) *nontemporal = c.nt;
+    return FDBB_OK;
+}
+
 int fdbb_kernel_info(int op, int dim, int dtype, int ppt, int nontemporal, int *vgprs, int *scratch_bytes)
 {
     if (op < 0 || op >= FDBB_NUM_OPS || dim < 1 || dim > 3 || (dtype != FDBB_F64 && dtype != FDBB_F32) ||
@@ -823,7 +888,7 @@ const char *fdbb_status_string(int status)
 
 const char *fdbb_last_error(void) { return g_last_error.c_str(); }
 
-int fdbb_version(void) { return 300; }
+int fdbb_version(void) { return 400; }
 
 }  // extern "C"
 

@@ -98,6 +98,9 @@ def library():
         lib.fdbb_set_launch_config.argtypes = [_i, _i, _i, _i, _i, _i, _i]
         lib.fdbb_get_launch_config.argtypes = [_i, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i),
                                                ctypes.POINTER(_i), ctypes.POINTER(_i)]
+        lib.fdbb_set_small_launch_config.argtypes = [_i, _i, _i, _i64, _i, _i, _i, _i]
+        lib.fdbb_get_small_launch_config.argtypes = [_i, _i, _i, ctypes.POINTER(_i64)] + [ctypes.POINTER(_i)] * 4
+        lib.fdbb_launch_config_for.argtypes = [_i, _i, _i, _i64] + [ctypes.POINTER(_i)] * 4
         lib.fdbb_kernel_info.argtypes = [_i, _i, _i, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]
         lib.fdbb_status_string.argtypes = [_i]
         lib.fdbb_status_string.restype = ctypes.c_char_p
@@ -378,6 +381,31 @@ def fdbb_get_launch_config(op, dim, dtype):
     op = OPS[op] if isinstance(op, str) else op
     b, p, g, t = _i(), _i(), _i(), _i()
     check(library().fdbb_get_launch_config(op, dim, dtype, ctypes.byref(b), ctypes.byref(p),
+                                           ctypes.byref(g), ctypes.byref(t)))
+    return b.value, p.value, g.value, t.value
+
+
+def fdbb_set_small_launch_config(op, dim, dtype, max_n, block=256, ppt=1, grid_cap=0, nontemporal=1):
+    """Configuration for calls of at most max_n points (max_n 0 removes it)."""
+    op = OPS[op] if isinstance(op, str) else op
+    check(library().fdbb_set_small_launch_config(op, dim, dtype, max_n, block, ppt, grid_cap, nontemporal))
+
+
+def fdbb_get_small_launch_config(op, dim, dtype):
+    """(max_n, block, ppt, grid_cap, nontemporal); max_n 0 when none is set."""
+    op = OPS[op] if isinstance(op, str) else op
+    m = _i64()
+    b, p, g, t = _i(), _i(), _i(), _i()
+    check(library().fdbb_get_small_launch_config(op, dim, dtype, ctypes.byref(m), ctypes.byref(b),
+                                                 ctypes.byref(p), ctypes.byref(g), ctypes.byref(t)))
+    return m.value, b.value, p.value, g.value, t.value
+
+
+def fdbb_launch_config_for(op, dim, dtype, n):
+    """(block, ppt, grid_cap, nontemporal) a call of n points launches with."""
+    op = OPS[op] if isinstance(op, str) else op
+    b, p, g, t = _i(), _i(), _i(), _i()
+    check(library().fdbb_launch_config_for(op, dim, dtype, n, ctypes.byref(b), ctypes.byref(p),
                                            ctypes.byref(g), ctypes.byref(t)))
     return b.value, p.value, g.value, t.value
 

@@ -14,6 +14,13 @@ The op ``batch`` tunes the persistent batch kernel (block x points per
 thread x workgroups per compute unit x store mode) on the 512-block batched
 workload and stores it as ``batch/3/<dtype>``; plans created without an
 explicit configuration, and the request server, use it.
+
+``--small N`` tunes the small-launch class instead: each candidate runs
+back to back over rotating copies of an N-point workload (about 1 GB in
+all, so that the last-level cache does not hold them), and a winner more
+than 2 % faster than the large configuration at that size is stored as
+``small/<op>/<dim>/<dtype>`` with max_n = 2N; calls of up to max_n points
+then launch with it (``fdbb_set_small_launch_config``).
 """
 from __future__ import annotations
 
@@ -168,6 +175,66 @@ def time_launch(fn, reps: int = 7, warmup: int = 2) -> float:
     return statistics.median(times)
 
 
+def time_queued(fns, launches: int = 256, rounds: int = 2) -> float:
+    """Milliseconds per launch of `launches` back-to-back launches cycling
+    over `fns` (one event pair around all of them; best of `rounds`)."""
+    for f in fns:
+        f()
+    stream = torch.cuda.current_stream()
+    best = float("inf")
+    for _ in range(rounds):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        for k in range(launches):
+            fns[k % len(fns)]()
+        b.record(stream)
+        b.synchronize()
+        best = min(best, a.elapsed_time(b) / launches)
+    return best
+
+
+SMALL_GRID_CAPS = (0, 2048)
+SMALL_MIN_GAIN = 0.02
+
+
+def search_small(op: str, dim: int, dt: str, n: int, verbose=False, target_bytes: float = 1e9):
+    """Tune the small-launch class at n points.  Returns (results sorted as
+    [(ms, cfg)], the large configuration's ms at this size, max_n installed
+    or 0).  Installs the winner for n <= 2n when it beats the large
+    configuration by more than SMALL_MIN_GAIN, else removes the entry."""
+    code, dtype = DT[dt]
+    es = 8 if dt == "f64" else 4
+    sets = max(1, min(64, math.ceil(target_bytes / (bytes_per_point(op, dim, es) * n))))
+    fns = [workload(op, dim, dtype, n) for _ in range(sets)]
+    large = F.fdbb_get_launch_config(op, dim, code)
+    F.fdbb_set_small_launch_config(op, dim, code, 0)
+    large_ms = time_queued(fns)
+    results = []
+    for cfg in itertools.product(BLOCKS, PPTS, SMALL_GRID_CAPS, STORE_MODES):
+        if F.fdbb_kernel_info(op, dim, code, cfg[1], cfg[3])[1] > 0:
+            continue
+        try:
+            F.fdbb_set_small_launch_config(op, dim, code, n, *cfg)
+            ms = time_queued(fns)
+        except F.FdbbError:
+            continue
+        results.append((ms, cfg))
+        if verbose:
+            print(f"  small {op} {dim}d {dt} n={n} cfg={cfg} {ms * 1e3:.2f} us", file=sys.stderr, flush=True)
+    results.sort()
+    max_n = 0
+    if results and results[0][0] < large_ms * (1 - SMALL_MIN_GAIN) and results[0][1] != large:
+        max_n = 2 * n
+        F.fdbb_set_small_launch_config(op, dim, code, max_n, *results[0][1])
+    else:
+        F.fdbb_set_small_launch_config(op, dim, code, 0)
+    del fns
+    torch.cuda.empty_cache()
+    return results, large_ms, max_n
+
+
 def search(op: str, dim: int, dt: str, n: int, reps: int = 7, space=None, verbose=False):
     """Time every candidate; returns [(ms, (block, ppt, grid_cap, nt))] sorted,
     and leaves the fastest installed."""
@@ -175,6 +242,10 @@ def search(op: str, dim: int, dt: str, n: int, reps: int = 7, space=None, verbos
     fn = workload(op, dim, dtype, n)
     space = space or list(itertools.product(BLOCKS, PPTS, GRID_CAPS, STORE_MODES))
     old = F.fdbb_get_launch_config(op, dim, code)
+    # a small-launch entry covering n would take over every candidate: lift it
+    small = F.fdbb_get_small_launch_config(op, dim, code)
+    if small[0] >= n:
+        F.fdbb_set_small_launch_config(op, dim, code, 0)
     results = []
     for cfg in space:
         # kernels that spill registers move extra bytes through HBM; skip them
@@ -190,6 +261,8 @@ def search(op: str, dim: int, dt: str, n: int, reps: int = 7, space=None, verbos
             print(f"  {op} {dim}d {dt} n={n} cfg={cfg} {ms:.4f} ms", file=sys.stderr, flush=True)
     results.sort()
     F.fdbb_set_launch_config(op, dim, code, *(results[0][1] if results else old))
+    if small[0] >= n:
+        F.fdbb_set_small_launch_config(op, dim, code, *small)
     return results
 
 
@@ -267,14 +340,21 @@ def apply_table(path: str = DEFAULT_TABLE, key: str | None = None) -> int:
     entries = table.get(key) or {}
     count = 0
     for name, e in entries.items():
-        op, dim, dt = name.split("/")
-        code = DT[dt][0]
+        parts = name.split("/")
         try:
+            if parts[0] == "small" and len(parts) == 4:
+                _, op, dim, dt = parts
+                F.fdbb_set_small_launch_config(op, int(dim), DT[dt][0], e["max_n"], e["block"], e["ppt"],
+                                               e["grid_cap"], e["nt"])
+                count += 1
+                continue
+            op, dim, dt = parts
+            code = DT[dt][0]
             if op == "batch":
                 F.fdbb_set_batch_config(code, e["block"], e["ppt"], e["grid_per_cu"], e["nt"])
             else:
                 F.fdbb_set_launch_config(op, int(dim), code, e["block"], e["ppt"], e["grid_cap"], e["nt"])
-        except F.FdbbError as exc:  # an entry the library no longer accepts keeps the default
+        except (F.FdbbError, KeyError, ValueError) as exc:  # an entry this library does not take
             print(f"fdbb: ignoring tuned entry {name}: {exc}", file=sys.stderr)
             continue
         count += 1
@@ -289,6 +369,8 @@ def main(argv=None):
     ap.add_argument("--n", default="auto",
                     help="points per launch, or 'auto' for a working set of about 2 GB per op")
     ap.add_argument("--reps", type=int, default=7)
+    ap.add_argument("--small", type=int, default=0,
+                    help="tune the small-launch class at this many points instead of the large one")
     ap.add_argument("--write", default=None, help="merge results into this JSON table")
     ap.add_argument("--verbose", action="store_true")
     args = ap.parse_args(argv)
@@ -313,6 +395,19 @@ def main(argv=None):
             continue
         for dim in (int(d) for d in args.dims.split(",")):
             for dt in args.dtypes.split(","):
+                if args.small:
+                    res, large_ms, max_n = search_small(op, dim, dt, args.small, verbose=args.verbose)
+                    name = f"small/{op}/{dim}/{dt}"
+                    info = {"n": args.small, "large_us": round(large_ms * 1e3, 3),
+                            "top5": [[round(ms * 1e3, 3), list(c)] for ms, c in res[:5]]}
+                    if max_n:
+                        block, ppt, cap, nt = res[0][1]
+                        entries[name] = {"max_n": max_n, "block": block, "ppt": ppt, "grid_cap": cap, "nt": nt,
+                                         "us": round(res[0][0] * 1e3, 3), **info}
+                    else:
+                        entries.pop(name, None)
+                    print(json.dumps({name: entries.get(name, {"kept_large": True, **info})}), flush=True)
+                    continue
                 n = (auto_size(op, dim, 8 if dt == "f64" else 4) if args.n == "auto" else int(args.n))
                 res = search(op, dim, dt, n, args.reps, verbose=args.verbose)
                 if not res:

@@ -252,6 +252,38 @@ def test_launch_config_table():
     assert F.fdbb_get_launch_config("flux", 3, 0) == old
 
 
+def test_small_launch_config_selects_by_size(lib):
+    op, dim, dt = "cons2prim", 1, F.F64
+    code = F.OPS[op]
+    large = F.fdbb_get_launch_config(op, dim, dt)
+    saved = F.fdbb_get_small_launch_config(op, dim, dt)
+    assert lib.fdbb_set_small_launch_config(code, dim, dt, -1, 256, 1, 0, 1) == F.EINVAL
+    assert lib.fdbb_set_small_launch_config(code, dim, dt, 100, 100, 1, 0, 1) == F.EINVAL
+    assert lib.fdbb_set_small_launch_config(code, dim, dt, 100, 256, 3, 0, 1) == F.EINVAL
+    assert lib.fdbb_set_small_launch_config(99, dim, dt, 100, 256, 1, 0, 1) == F.EINVAL
+    assert lib.fdbb_set_small_launch_config(F.OPS["fused"], 3, dt, 100, 512, 1, 0, 1) == F.EINVAL  # staged
+    assert lib.fdbb_launch_config_for(code, dim, dt, -1, None, None, None, None) == F.EINVAL
+    try:
+        F.fdbb_set_small_launch_config(op, dim, dt, 0)
+        assert F.fdbb_get_small_launch_config(op, dim, dt) == (0, *large)
+        for n in (0, 1, 1 << 20, 1 << 30):
+            assert F.fdbb_launch_config_for(op, dim, dt, n) == large
+        small = (128, 4, 0, 0) if large != (128, 4, 0, 0) else (64, 2, 0, 1)
+        F.fdbb_set_small_launch_config(op, dim, dt, 1 << 21, *small)
+        assert F.fdbb_get_small_launch_config(op, dim, dt) == (1 << 21, *small)
+        assert F.fdbb_launch_config_for(op, dim, dt, 1) == small
+        assert F.fdbb_launch_config_for(op, dim, dt, 1 << 21) == small
+        assert F.fdbb_launch_config_for(op, dim, dt, (1 << 21) + 1) == large
+        # other (op, dim, dtype) keys are untouched
+        assert F.fdbb_launch_config_for(op, 2, dt, 1) == F.fdbb_get_launch_config(op, 2, dt)
+        assert F.fdbb_launch_config_for(op, dim, F.F32, 1) == F.fdbb_get_launch_config(op, dim, F.F32)
+        F.fdbb_set_small_launch_config(op, dim, dt, 0)
+        assert F.fdbb_launch_config_for(op, dim, dt, 1) == large
+    finally:
+        F.fdbb_set_small_launch_config(op, dim, dt, *saved) if saved[0] else \
+            F.fdbb_set_small_launch_config(op, dim, dt, 0)
+
+
 def test_kernel_info_rejects_bad_arguments():
     lib = F.library()
     assert lib.fdbb_kernel_info(3, 3, 0, 3, 1, None, None) == F.EINVAL

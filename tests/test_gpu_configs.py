@@ -18,12 +18,20 @@ def _gpu():
 
 
 def _with_config(op, dim, dt_code, cfg, fn):
+    """Run fn with cfg as the only configuration of (op, dim, dtype): the
+    small-launch entry, which would take over at these sizes, is lifted for
+    the call."""
     old = F.fdbb_get_launch_config(op, dim, dt_code)
+    small = F.fdbb_get_small_launch_config(op, dim, dt_code)
     F.fdbb_set_launch_config(op, dim, dt_code, *cfg)
+    F.fdbb_set_small_launch_config(op, dim, dt_code, 0)
     try:
+        assert F.fdbb_launch_config_for(op, dim, dt_code, 1) == tuple(cfg)
         return fn()
     finally:
         F.fdbb_set_launch_config(op, dim, dt_code, *old)
+        if small[0]:
+            F.fdbb_set_small_launch_config(op, dim, dt_code, *small)
 
 
 @pytest.mark.parametrize("block,ppt,grid,nt", CONFIGS)
@@ -108,3 +116,37 @@ def test_eigen_adjoint_roe_all_configs(block, ppt, grid, nt):
         URo, URg = states(dim, n, 92, dt)
         Uh = _with_config("roe_average", dim, code, cfg, lambda: F.roe_average(Ug, URg, GAMMA))
         assert roe_error(host(Uh), oracle.roe_average(dim, GAMMA, Uo, URo), Uo, URo) <= TOL[dt]
+
+
+def test_shipped_small_entries_are_what_small_calls_use():
+    """The shipped table gives calls of up to max_n points their own launch
+    configuration, and calls above it the large one."""
+    from paper_1809_09851_amd import tune
+    entries = (tune.load_table() or {}).get(tune.arch_key(), {})
+    small = {k: v for k, v in entries.items() if k.startswith("small/")}
+    assert len(small) > 50
+    for name, e in small.items():
+        _, op, dim, dt = name.split("/")
+        code, dim = tune.DT[dt][0], int(dim)
+        assert F.fdbb_get_small_launch_config(op, dim, code) == (
+            e["max_n"], e["block"], e["ppt"], e["grid_cap"], e["nt"]), name
+        assert F.fdbb_launch_config_for(op, dim, code, e["max_n"] + 1) == F.fdbb_get_launch_config(op, dim, code)
+
+
+@pytest.mark.parametrize("op", ["cons2prim", "eos", "flux"])
+def test_1d_ops_on_both_sides_of_the_small_bound(op):
+    """The 1D ops of a step at the last size of the small class and the
+    first of the large one, every point against the oracle."""
+    m = F.fdbb_get_small_launch_config(op, 1, F.F64)[0]
+    assert m > 0
+    for n in (m, m + 1):
+        Uo, Ug = states(1, n, 90 + (n & 1), "f64")
+        if op == "cons2prim":
+            assert group_error(host(F.cons2prim(Ug, GAMMA)), oracle.cons2prim(1, GAMMA, Uo), state_groups(1)) <= TOL["f64"]
+        elif op == "eos":
+            p, c = F.eos(Ug, GAMMA)
+            po, co = oracle.eos(1, GAMMA, Uo)
+            assert group_error(host(p)[None], po[None], [[0]]) <= TOL["f64"]
+            assert group_error(host(c)[None], co[None], [[0]]) <= TOL["f64"]
+        else:
+            assert group_error(host(F.flux(Ug, GAMMA)), oracle.flux(1, GAMMA, Uo), flux_groups(1)) <= TOL["f64"]

@@ -54,6 +54,52 @@ def test_table_round_trip(tmp_path, monkeypatch):
         F.fdbb_set_launch_config("flux", 3, F.F64, *old)
 
 
+def test_table_round_trip_small_entries(tmp_path):
+    p = tmp_path / "t.json"
+    key = "gfx950/hiptest"
+    p.write_text(json.dumps({key: {
+        "small/flux/1/f64": {"max_n": 1 << 21, "block": 64, "ppt": 1, "grid_cap": 0, "nt": 1},
+        "small/fused/3/f64": {"max_n": 1 << 21, "block": 1024, "ppt": 1, "grid_cap": 0, "nt": 1},  # refused
+        "small/flux/1": {"max_n": 1},                                                            # malformed
+    }}))
+    saved = F.fdbb_get_small_launch_config("flux", 1, F.F64)
+    try:
+        assert tune.apply_table(str(p), key=key) == 1
+        assert F.fdbb_get_small_launch_config("flux", 1, F.F64) == (1 << 21, 64, 1, 0, 1)
+        assert F.fdbb_get_small_launch_config("fused", 3, F.F64)[0] == 0
+    finally:
+        F.fdbb_set_small_launch_config("flux", 1, F.F64, *saved) if saved[0] else \
+            F.fdbb_set_small_launch_config("flux", 1, F.F64, 0)
+
+
+def test_search_small_installs_only_a_clear_winner(monkeypatch):
+    """The small class is stored only when its best shape beats the large
+    configuration at that size by more than the margin."""
+    monkeypatch.setattr(tune, "workload", lambda op, dim, dtype, n: (lambda: None))
+    monkeypatch.setattr(F, "fdbb_kernel_info", lambda *a, **k: (128, 0))
+    op, dim, dt = "eos", 1, F.F64
+    large = F.fdbb_get_launch_config(op, dim, dt)
+
+    def clock(win):
+        def t(fns, launches=256, rounds=2):
+            m, b, p, g, nt = F.fdbb_get_small_launch_config(op, dim, dt)
+            cfg = (b, p, g, nt)
+            return 1.0 - (win if (m and cfg == (512, 2, 0, 1)) else 0.0)
+        return t
+    try:
+        monkeypatch.setattr(tune, "time_queued", clock(0.10))
+        res, large_ms, max_n = tune.search_small(op, dim, "f64", 1 << 20)
+        assert large_ms == 1.0 and max_n == 1 << 21 and res[0][1] == (512, 2, 0, 1)
+        assert F.fdbb_get_small_launch_config(op, dim, dt) == (1 << 21, 512, 2, 0, 1)
+        assert F.fdbb_launch_config_for(op, dim, dt, 1 << 20) == (512, 2, 0, 1)
+        assert F.fdbb_launch_config_for(op, dim, dt, 1 << 22) == large
+        monkeypatch.setattr(tune, "time_queued", clock(0.01))
+        res, large_ms, max_n = tune.search_small(op, dim, "f64", 1 << 20)
+        assert max_n == 0 and F.fdbb_get_small_launch_config(op, dim, dt)[0] == 0
+    finally:
+        F.fdbb_set_small_launch_config(op, dim, dt, 0)
+
+
 def test_main_skips_an_op_with_no_usable_configuration(tmp_path, monkeypatch):
     """When every configuration spills (or is refused), the tuner reports it
     and writes no entry instead of failing."""
