@@ -339,7 +339,11 @@ int fdbb_batch_plan_update(fdbb_batch_plan *plan, const fdbb_task *tasks, int nt
                            void *stream);
 
 /* Run the plan's persistent launch on `stream`: use_graph != 0 replays the
- * captured HIP graph, 0 launches the same kernel directly. */
+ * captured HIP graph, 0 launches the same kernel directly.  The graph was
+ * captured with the LDS the plan reserved at creation (a plan created empty
+ * reserves 3D FP64 Jacobian staging, which leaves room for one or two
+ * workgroups per compute unit); a direct launch takes only what the current
+ * task list stages, none for a list without Jacobian blocks. */
 int fdbb_batch_exec(fdbb_batch_plan *plan, void *stream, int use_graph);
 
 /* The batch configuration that plans created with block == 0, the
@@ -352,6 +356,16 @@ int fdbb_batch_exec(fdbb_batch_plan *plan, void *stream, int use_graph);
  * or a configuration whose 3D Jacobian staging would not fit in LDS. */
 int fdbb_set_batch_config(int dtype, int block, int ppt, int grid_per_cu, int nontemporal);
 int fdbb_get_batch_config(int dtype, int *block, int *ppt, int *grid_per_cu, int *nontemporal);
+
+/* The batch configuration of the request server's batched launches, whose
+ * task mix (small requests of every op, dim and storage type) wants another
+ * shape than a batch of fused passes.  Same ranges and checks as
+ * fdbb_set_batch_config (3D FP64 Jacobian staging must fit); block 0
+ * removes the entry, and until one is installed the server takes the FP64
+ * batch configuration, which the getter then reports.  Servers read it when
+ * they are created. */
+int fdbb_set_server_batch_config(int block, int ppt, int grid_per_cu, int nontemporal);
+int fdbb_get_server_batch_config(int *block, int *ppt, int *grid_per_cu, int *nontemporal);
 
 /* The launch configuration a plan was created with (any may be NULL). */
 int fdbb_batch_plan_config(const fdbb_batch_plan *plan, int *block, int *ppt, int *grid,

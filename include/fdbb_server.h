@@ -7,7 +7,8 @@
  * scheduler thread admits queued requests in arrival order while a launch
  * slot is free and their outputs fit in the server's device arena (the HBM
  * budget), runs every request admitted into a slot as one persistent batch
- * launch (FDBB_SERVE_BATCHED: continuous batching, one stream per slot) or
+ * launch (FDBB_SERVE_BATCHED: continuous batching, one stream per slot,
+ * launched with the configuration of fdbb_set_server_batch_config) or
  * each as its own launch on one stream (FDBB_SERVE_SINGLE: the
  * one-launch-per-request baseline), and reports a request complete when its
  * launch's completion event fires.  Outputs stay in the arena, with the

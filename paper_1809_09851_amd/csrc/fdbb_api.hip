@@ -146,7 +146,8 @@ struct BatchConfig {
     int nt;  // 0 regular, 1 nt, 2 nt + sc1
 };
 
-std::atomic<uint64_t> g_batch_cfg[2] = {{0}, {0}};
+// [0] FP64, [1] FP32, [2] the request server's batched launches
+std::atomic<uint64_t> g_batch_cfg[3] = {{0}, {0}, {0}};
 
 uint64_t pack_batch(const BatchConfig &c)
 {
@@ -154,9 +155,10 @@ uint64_t pack_batch(const BatchConfig &c)
            ((uint64_t)(uint32_t)c.grid_per_cu << 32);
 }
 
+// dtype FDBB_F64 or FDBB_F32, or 2 for the server's entry
 BatchConfig get_batch_config(int dtype)
 {
-    const uint64_t v = g_batch_cfg[dtype == FDBB_F32 ? 1 : 0].load(std::memory_order_relaxed);
+    const uint64_t v = g_batch_cfg[dtype == FDBB_F32 ? 1 : (dtype == 2 ? 2 : 0)].load(std::memory_order_relaxed);
     if (v == 0) return BatchConfig{256, 1, 0, 1};
     BatchConfig c;
     c.block = (int)(v & 0xffff);
@@ -911,7 +913,8 @@ struct fdbb_batch_plan {
     int ppt = 1;
     int grid = 0;
     int nt = 1;
-    size_t lds = 0;
+    size_t lds = 0;      // reserved at creation: what the captured graph launches with
+    size_t cur_lds = 0;  // what the current task list needs: direct launches use it
     int64_t points = 0;
     int64_t tiles = 0;
     const void *kernel = nullptr;
@@ -1015,6 +1018,7 @@ int stage_tasks(fdbb_batch_plan *p, const fdbb_task *tasks, int ntasks)
     p->ntasks = ntasks;
     p->tiles = info.tiles;
     p->points = info.points;
+    p->cur_lds = info.lds;
     return FDBB_OK;
 }
 
@@ -1029,14 +1033,18 @@ int upload(fdbb_batch_plan *p, hipStream_t s)
     return FDBB_OK;
 }
 
-int launch_plan(fdbb_batch_plan *p, hipStream_t s)
+// The persistent launch of p's table with `lds` bytes of dynamic LDS (the
+// reserve when captured into the graph, the current list's need when
+// launched directly: a list without Jacobian staging then runs at full
+// occupancy).
+int launch_plan(fdbb_batch_plan *p, hipStream_t s, size_t lds)
 {
     unsigned char *d = p->dev;
     const TaskDev *tasks = p->tasks(d);
     const int64_t *prefix = p->prefix(d);
     const int64_t *header = p->header(d);
     void *args[] = {&tasks, &prefix, &header};
-    hipError_t e = hipLaunchKernel(p->kernel, dim3((unsigned)p->grid), dim3((unsigned)p->block), args, p->lds, s);
+    hipError_t e = hipLaunchKernel(p->kernel, dim3((unsigned)p->grid), dim3((unsigned)p->block), args, lds, s);
     if (e != hipSuccess) return fail_hip(e, "batch kernel launch");
     return FDBB_OK;
 }
@@ -1144,7 +1152,7 @@ int fdbb_batch_plan_create(const fdbb_task *tasks, int ntasks, int capacity, int
     }
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        rc = launch_plan(p, cs);
+        rc = launch_plan(p, cs, p->lds);
         hipError_t e2 = hipStreamEndCapture(cs, &p->graph);
         if (rc == FDBB_OK && e2 != hipSuccess) rc = fail_hip(e2, "hipStreamEndCapture");
     } else {
@@ -1183,7 +1191,7 @@ int fdbb_batch_exec(fdbb_batch_plan *plan, void *stream, int use_graph)
         if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
         return FDBB_OK;
     }
-    return launch_plan(plan, (hipStream_t)stream);
+    return launch_plan(plan, (hipStream_t)stream, plan->cur_lds);
 }
 
 int fdbb_set_batch_config(int dtype, int block, int ppt, int grid_per_cu, int nontemporal)
@@ -1196,6 +1204,32 @@ int fdbb_set_batch_config(int dtype, int block, int ppt, int grid_per_cu, int no
     if (lds_bytes(FDBB_OP_FLUX_JACOBIAN, 3, dtype, block, ppt) > 160 * 1024)
         return fail(FDBB_EINVAL, "batch configuration needs more LDS than a workgroup may use");
     g_batch_cfg[dtype == FDBB_F32 ? 1 : 0].store(pack_batch(BatchConfig{block, ppt, grid_per_cu, nontemporal}));
+    return FDBB_OK;
+}
+
+int fdbb_set_server_batch_config(int block, int ppt, int grid_per_cu, int nontemporal)
+{
+    g_last_error.clear();
+    if (block == 0) {
+        g_batch_cfg[2].store(0);
+        return FDBB_OK;
+    }
+    if (!batch_config_ok(block, ppt, nontemporal) || grid_per_cu < 0 || grid_per_cu > 64)
+        return fail(FDBB_EINVAL, "invalid batch configuration");
+    if (lds_bytes(FDBB_OP_FLUX_JACOBIAN, 3, FDBB_F64, block, ppt) > 160 * 1024)
+        return fail(FDBB_EINVAL, "batch configuration needs more LDS than a workgroup may use");
+    g_batch_cfg[2].store(pack_batch(BatchConfig{block, ppt, grid_per_cu, nontemporal}));
+    return FDBB_OK;
+}
+
+int fdbb_get_server_batch_config(int *block, int *ppt, int *grid_per_cu, int *nontemporal)
+{
+    const uint64_t v = g_batch_cfg[2].load(std::memory_order_relaxed);
+    const BatchConfig c = v ? get_batch_config(2) : get_batch_config(FDBB_F64);
+    if (block) *block = c.block;
+    if (ppt) *ppt = c.ppt;
+    if (grid_per_cu) *grid_per_cu = c.grid_per_cu;
+    if (nontemporal) *nontemporal = c.nt;
     return FDBB_OK;
 }
 

@@ -1,8 +1,9 @@
 // Native request server (declared in include/fdbb_server.h): a scheduler
 // thread admits queued requests in arrival order while a launch slot is free
 // and their outputs fit in a device arena of the budget's size, packs them
-// into one persistent batch launch per slot (replaying the slot's HIP
-// graph), and retires them when the slot's completion event fires.  Outputs
+// into one persistent batch launch per slot (a direct launch of the slot's
+// plan, with the server's batch configuration and the LDS its list
+// stages), and retires them when the slot's completion event fires.  Outputs
 // live in the arena until the caller releases them.
 #include "../../include/fdbb_server.h"
 
@@ -232,7 +233,7 @@ int launch(fdbb_server *s, Slot &slot)
             if ((rc = fdbb_task_run(&t, slot.stream))) break;
     } else {
         rc = fdbb_batch_plan_update(slot.plan, tasks.data(), (int)tasks.size(), slot.stream);
-        if (!rc) rc = fdbb_batch_exec(slot.plan, slot.stream, 1);
+        if (!rc) rc = fdbb_batch_exec(slot.plan, slot.stream, 0);
     }
     if (!rc && hipEventRecord(slot.done, slot.stream) != hipSuccess) rc = FDBB_EHIP;
     return rc;
@@ -338,6 +339,18 @@ int fdbb_server_create(int64_t budget_bytes, int slots, int max_batch, double ma
         fdbb_server_destroy(s);
         return FDBB_EHIP;
     }
+    // Batched launches take the server's batch configuration (its grid sized
+    // to this device) and reserve LDS for any task; each launch is direct,
+    // with the LDS its own task list stages.
+    int block = 0, ppt = 0, grid_per_cu = 0, nt = 0, cus = 0;
+    if (mode == FDBB_SERVE_BATCHED) {
+        fdbb_get_server_batch_config(&block, &ppt, &grid_per_cu, &nt);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess) {
+            fdbb_server_destroy(s);
+            return FDBB_EHIP;
+        }
+    }
+    const int grid = cus * (grid_per_cu > 0 ? grid_per_cu : std::max(1, 2048 / std::max(1, block)));
     s->slots.resize(slots);
     for (Slot &slot : s->slots) {
         if (mode == FDBB_SERVE_SINGLE) slot.stream = s->single_stream;
@@ -350,7 +363,7 @@ int fdbb_server_create(int64_t budget_bytes, int slots, int max_batch, double ma
             return FDBB_EHIP;
         }
         if (mode == FDBB_SERVE_BATCHED &&
-            (rc = fdbb_batch_plan_create(nullptr, 0, std::max(1, max_batch), 0, 0, 0, 0, &slot.plan))) {
+            (rc = fdbb_batch_plan_create(nullptr, 0, std::max(1, max_batch), block, ppt, grid, nt, &slot.plan))) {
             fdbb_server_destroy(s);
             return rc;
         }

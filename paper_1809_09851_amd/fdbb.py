@@ -116,6 +116,8 @@ def library():
         lib.fdbb_set_batch_config.argtypes = [_i, _i, _i, _i, _i]
         lib.fdbb_get_batch_config.argtypes = [_i] + [ctypes.POINTER(_i)] * 4
         lib.fdbb_batch_plan_config.argtypes = [_p] + [ctypes.POINTER(_i)] * 4
+        lib.fdbb_set_server_batch_config.argtypes = [_i, _i, _i, _i]
+        lib.fdbb_get_server_batch_config.argtypes = [ctypes.POINTER(_i)] * 4
         lib.fdbb_batch_run_noalloc.argtypes = [ctypes.POINTER(Task), _i, _i, _i, _i, _i, _p]
         lib.fdbb_task_check.argtypes = [ctypes.POINTER(Task)]
         lib.fdbb_task_run.argtypes = [ctypes.POINTER(Task), _p]
@@ -407,6 +409,19 @@ def fdbb_launch_config_for(op, dim, dtype, n):
     b, p, g, t = _i(), _i(), _i(), _i()
     check(library().fdbb_launch_config_for(op, dim, dtype, n, ctypes.byref(b), ctypes.byref(p),
                                            ctypes.byref(g), ctypes.byref(t)))
+    return b.value, p.value, g.value, t.value
+
+
+def fdbb_set_server_batch_config(block, ppt=1, grid_per_cu=0, nontemporal=1):
+    """Batch configuration of the request server's launches (block 0 removes it)."""
+    check(library().fdbb_set_server_batch_config(block, ppt, grid_per_cu, nontemporal))
+
+
+def fdbb_get_server_batch_config():
+    """(block, ppt, grid_per_cu, nontemporal) the request server launches with."""
+    b, p, g, t = _i(), _i(), _i(), _i()
+    check(library().fdbb_get_server_batch_config(ctypes.byref(b), ctypes.byref(p), ctypes.byref(g),
+                                                 ctypes.byref(t)))
     return b.value, p.value, g.value, t.value
 
 

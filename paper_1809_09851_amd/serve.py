@@ -222,34 +222,48 @@ def allocate_output(r: Request, stream):
         return F.empty_blocks(r.dim, r.n, dtype)
 
 
+def batch_task(r: Request):
+    """The batch task of an admitted request (its output allocated)."""
+    from . import batch as B
+    if r.op == "cons2prim":
+        return B.cons2prim_task(r.U, r.out, r.gamma)
+    if r.op == "flux":
+        return B.flux_task(r.U, r.out, r.gamma)
+    if r.op == "flux_jacobian":
+        return B.jacobian_task(r.U, r.out, r.gamma)
+    return B.adjoint_task(r.U, r.Fbar, r.out, r.gamma)
+
+
 class GpuBatchExecutor:
     """One batch plan and one stream per slot; a launch packs all of its
-    requests into the plan's task table and replays the plan's graph."""
+    requests into the plan's task table and launches the plan directly, with
+    the LDS its task list stages."""
 
     def __init__(self, slots: int, capacity: int = 256, block: int = 0, ppt: int = 1):
         import torch
 
         from . import batch as B
+        from . import fdbb as F
         self.torch = torch
         self.B = B
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
         # empty plans reserve LDS for any task (3D FP64 Jacobian staging);
-        # block 0 takes the autotuned batch configuration
-        self.plans = [B.Plan([], capacity=capacity, block=block, ppt=ppt) for _ in range(slots)]
+        # block 0 takes the server's batch configuration, as the native server
+        if block == 0:
+            block, ppt, gpc, nt = F.fdbb_get_server_batch_config()
+            cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+            grid = cus * (gpc if gpc > 0 else max(1, 2048 // block))
+        else:
+            grid, nt = 0, 1
+        self.plans = [B.Plan([], capacity=capacity, block=block, ppt=ppt, grid=grid, nontemporal=nt)
+                      for _ in range(slots)]
         self.events = [None] * slots
 
     def allocate(self, r: Request, stream):
         return allocate_output(r, stream)
 
     def task(self, r: Request):
-        B = self.B
-        if r.op == "cons2prim":
-            return B.cons2prim_task(r.U, r.out, r.gamma)
-        if r.op == "flux":
-            return B.flux_task(r.U, r.out, r.gamma)
-        if r.op == "flux_jacobian":
-            return B.jacobian_task(r.U, r.out, r.gamma)
-        return B.adjoint_task(r.U, r.Fbar, r.out, r.gamma)
+        return batch_task(r)
 
     def launch(self, slot: int, batch):
         s = self.streams[slot]
@@ -262,7 +276,7 @@ class GpuBatchExecutor:
         else:
             plan = self.plans[slot]
             plan.update([self.task(r) for r in batch], stream=s)
-            plan.run(stream=s, graph=True)
+            plan.run(stream=s, graph=False)
         ev = self.torch.cuda.Event()
         ev.record(s)
         self.events[slot] = ev

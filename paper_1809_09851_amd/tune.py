@@ -15,6 +15,9 @@ thread x workgroups per compute unit x store mode) on the 512-block batched
 workload and stores it as ``batch/3/<dtype>``; plans created without an
 explicit configuration, and the request server, use it.
 
+The op ``serve`` tunes the request server's batch configuration on
+batches packed from the serving request mix (``serve_batch/0/mix``).
+
 ``--small N`` tunes the small-launch class instead: each candidate runs
 back to back over rotating copies of an N-point workload (about 1 GB in
 all, so that the last-level cache does not hold them), and a winner more
@@ -319,6 +322,86 @@ def search_batch(dt: str, reps: int = 5, space=None, verbose=False, nblocks: int
     return results, points
 
 
+def serve_workload(batches: int = 24, seed: int = 7, max_batch: int = 64, max_bytes: float = 64e6):
+    """Batches as the request server packs them from the serving request mix
+    (inputs.request_stream: the server's ops, D in {1, 2, 3}, N log-uniform
+    in [10^3, 10^7], FP64 or FP32, inputs viewed from device-resident state
+    pools): consecutive requests while a batch holds at most max_batch
+    requests and max_bytes moved bytes.  A request larger than that runs
+    alone in the server, not in a batch, and is left out.  Returns (task
+    lists, moved bytes of one pass, what the tasks point into)."""
+    from . import inputs
+    from . import serve
+    pools = serve.StatePools(pool=10_000_000, seed=4)
+    specs = inputs.request_stream(1e6, 40 * batches * max_batch, seed=seed, pool=pools.pool)
+    lists, keep, total = [], [pools], 0
+    cur, cur_bytes = [], 0
+    for spec in specs:
+        r = pools.request(spec)
+        m = serve.moved_bytes(r.op, r.dim, r.n, r.elem)
+        if m > max_bytes:
+            continue
+        if cur and (len(cur) == max_batch or cur_bytes + m > max_bytes):
+            lists.append(cur)
+            total += cur_bytes
+            cur, cur_bytes = [], 0
+            if len(lists) == batches:
+                break
+        r.out = serve.allocate_output(r, torch.cuda.current_stream())
+        keep.append(r)
+        cur.append(serve.batch_task(r))
+        cur_bytes += m
+    torch.cuda.synchronize()
+    return lists, total, keep
+
+
+def search_serve(reps: int = 3, space=None, verbose=False, batches: int = 24):
+    """Time every batch configuration on the server's batches (each a direct
+    launch of an empty-created plan updated with the batch, as the server
+    runs them); returns [(ms per pass over the batches, (block, ppt,
+    grid_per_cu, nt))] sorted, the FP64 batch configuration's ms, and the
+    moved bytes of one pass, and installs the fastest as the server's."""
+    from . import batch as B
+    lists, total, keep = serve_workload(batches)
+    cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    space = space or list(itertools.product(BATCH_BLOCKS, BATCH_PPTS, BATCH_GRID_PER_CU, BATCH_STORE_MODES))
+    cap = max(len(t) for t in lists)
+
+    def one(cfg):
+        block, ppt, gpc, nt = cfg
+        plan = B.Plan([], capacity=cap, block=block, ppt=ppt, grid=cus * (gpc or max(1, 2048 // block)),
+                      nontemporal=nt)
+
+        def run():
+            for tasks in lists:
+                plan.update(tasks)
+                plan.run(graph=False)
+        try:
+            return time_launch(run, reps, 1)
+        finally:
+            plan.close()
+
+    results = []
+    for cfg in space:
+        if cfg[0] * cfg[1] * 25 * 8 > 160 * 1024:  # 3D FP64 Jacobian staging must fit in LDS
+            continue
+        try:
+            ms = one(cfg)
+        except F.FdbbError:
+            continue
+        results.append((ms, cfg))
+        if verbose:
+            print(f"  serve cfg={cfg} {ms:.4f} ms", file=sys.stderr, flush=True)
+    results.sort()
+    base = F.fdbb_get_batch_config(F.F64)
+    base_ms = dict((c, ms) for ms, c in results).get(tuple(base))
+    if results:
+        F.fdbb_set_server_batch_config(*results[0][1])
+    del keep, lists
+    torch.cuda.empty_cache()
+    return results, base_ms, total
+
+
 def load_table(path: str = DEFAULT_TABLE):
     try:
         with open(path) as f:
@@ -342,6 +425,10 @@ def apply_table(path: str = DEFAULT_TABLE, key: str | None = None) -> int:
     for name, e in entries.items():
         parts = name.split("/")
         try:
+            if parts[0] == "serve_batch":
+                F.fdbb_set_server_batch_config(e["block"], e["ppt"], e["grid_per_cu"], e["nt"])
+                count += 1
+                continue
             if parts[0] == "small" and len(parts) == 4:
                 _, op, dim, dt = parts
                 F.fdbb_set_small_launch_config(op, int(dim), DT[dt][0], e["max_n"], e["block"], e["ppt"],
@@ -379,6 +466,16 @@ def main(argv=None):
     table = (load_table(args.write) if args.write else None) or {}
     entries = table.setdefault(key, {})
     for op in args.ops.split(","):
+        if op == "serve":
+            res, base_ms, total = search_serve(max(3, args.reps - 4), verbose=args.verbose)
+            if res:
+                best_ms, (block, ppt, gpc, nt) = res[0]
+                entries["serve_batch/0/mix"] = {"block": block, "ppt": ppt, "grid_per_cu": gpc, "nt": nt,
+                                                "ms": round(best_ms, 5), "bytes": total,
+                                                "fp64_batch_config_ms": round(base_ms, 5) if base_ms else None,
+                                                "top5": [[round(ms, 5), list(c)] for ms, c in res[:5]]}
+                print(json.dumps({"serve_batch/0/mix": entries["serve_batch/0/mix"]}), flush=True)
+            continue
         if op == "batch":
             # the batched workload is 3D whatever --dims says
             for dt in args.dtypes.split(","):

@@ -149,6 +149,28 @@ def test_batch_config_table():
         F.fdbb_set_batch_config(F.F64, *old)
 
 
+def test_server_batch_config():
+    lib = F.library()
+    old64 = F.fdbb_get_batch_config(F.F64)
+    saved = F.fdbb_get_server_batch_config()
+    try:
+        F.fdbb_set_server_batch_config(0)                     # no entry: the FP64 batch configuration
+        assert F.fdbb_get_server_batch_config() == old64
+        assert lib.fdbb_set_server_batch_config(256, 1, 8, 1) == F.OK
+        assert F.fdbb_get_server_batch_config() == (256, 1, 8, 1)
+        assert F.fdbb_get_batch_config(F.F64) == old64        # the batch table is not touched
+        assert lib.fdbb_set_server_batch_config(256, 4, 0, 1) == F.EINVAL   # 3D FP64 staging beyond LDS
+        assert lib.fdbb_set_server_batch_config(96, 1, 0, 1) == F.EINVAL
+        assert lib.fdbb_set_server_batch_config(64, 3, 0, 1) == F.EINVAL
+        assert lib.fdbb_set_server_batch_config(64, 1, 65, 1) == F.EINVAL
+        assert lib.fdbb_set_server_batch_config(64, 1, 0, 3) == F.EINVAL
+        assert F.fdbb_get_server_batch_config() == (256, 1, 8, 1)
+        F.fdbb_set_server_batch_config(0)
+        assert F.fdbb_get_server_batch_config() == old64
+    finally:
+        F.fdbb_set_server_batch_config(*saved)
+
+
 def test_eigen_and_char_apply_checks():
     lib = F.library()
     assert lib.fdbb_eigenvectors(3, 1.4, 0, A0, 128, None, 0, None, 0, 100, None) == F.EINVAL

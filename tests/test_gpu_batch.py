@@ -242,3 +242,47 @@ def test_flux_direction_tasks_in_a_plan(dt):
         assert group_error(host(Fd), oracle.flux(dim, GAMMA, Uo)[d::dim], [g]) <= TOL[dt]
         assert group_error(host(Fd), host(F.flux(Ug, GAMMA, direction=d)), [g]) <= TOL[dt]
     plan.close()
+
+
+def test_direct_launches_size_lds_to_the_task_list():
+    """A plan created empty reserves 3D FP64 Jacobian staging for its graph;
+    a direct launch takes only what the current list stages.  Lists without
+    Jacobian blocks, then with 3D FP64 ones, then without again, direct and
+    replayed, all against the oracle."""
+    plan = B.Plan([], capacity=16, block=256, ppt=2)
+    rng = np.random.default_rng(31)
+    for rnd, with_jac in enumerate((False, True, False)):
+        checks, tasks, inputs_alive = [], [], []
+        for k in range(8):
+            dim, dt = 1 + k % 3, ("f64", "f32")[(k // 3) % 2]
+            n = int(rng.integers(1, 9000))
+            Uo, Ug = states(dim, n, 500 + 10 * rnd + k, dt)
+            if with_jac and k % 2 == 0:
+                Uo, Ug = states(3, n, 600 + 10 * rnd + k, "f64")
+                A = F.empty_blocks(3, n)
+                tasks.append(B.jacobian_task(Ug, A, GAMMA))
+                checks.append(("jac", "f64", Uo, A))
+            elif k % 2 == 0:
+                V = F.empty_fields(dim + 2, n, Ug.dtype)
+                tasks.append(B.cons2prim_task(Ug, V, GAMMA))
+                checks.append(("c2p", dt, Uo, V))
+            else:
+                Fo = F.empty_fields((dim + 2) * dim, n, Ug.dtype)
+                tasks.append(B.flux_task(Ug, Fo, GAMMA))
+                checks.append(("flux", dt, Uo, Fo))
+            inputs_alive.append(Ug)  # the tasks hold raw pointers
+        plan.update(tasks)
+        for graph in (False, True):
+            for *_, out in checks:
+                out.zero_()
+            plan.run(graph=graph)
+            torch.cuda.synchronize()
+            for kind, dt, Uo, out in checks:
+                dim = Uo.shape[0] - 2
+                if kind == "jac":
+                    assert blocks_error(host(out), oracle.flux_jacobian(3, GAMMA, Uo)) <= TOL[dt]
+                elif kind == "c2p":
+                    assert group_error(host(out), oracle.cons2prim(dim, GAMMA, Uo), state_groups(dim)) <= TOL[dt]
+                else:
+                    assert group_error(host(out), oracle.flux(dim, GAMMA, Uo), flux_groups(dim)) <= TOL[dt]
+    plan.close()

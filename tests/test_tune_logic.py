@@ -72,6 +72,18 @@ def test_table_round_trip_small_entries(tmp_path):
             F.fdbb_set_small_launch_config("flux", 1, F.F64, 0)
 
 
+def test_table_installs_the_server_batch_entry(tmp_path):
+    p = tmp_path / "t.json"
+    key = "gfx950/hiptest"
+    p.write_text(json.dumps({key: {"serve_batch/0/mix": {"block": 128, "ppt": 2, "grid_per_cu": 8, "nt": 1}}}))
+    saved = F.fdbb_get_server_batch_config()
+    try:
+        assert tune.apply_table(str(p), key=key) == 1
+        assert F.fdbb_get_server_batch_config() == (128, 2, 8, 1)
+    finally:
+        F.fdbb_set_server_batch_config(*saved)
+
+
 def test_search_small_installs_only_a_clear_winner(monkeypatch):
     """The small class is stored only when its best shape beats the large
     configuration at that size by more than the margin."""
