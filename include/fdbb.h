@@ -36,8 +36,9 @@
  * that point.  Only launch errors are reported, not asynchronous faults.
  * Validation (host side, before any HIP call):
  *   FDBB_EINVAL  dim not in {1,2,3}, gamma not finite or <= 1, unknown dtype,
- *                n < 0, a direction out of range, a NULL required pointer
- *                with n > 0, or ld < n;
+ *                n < 0 or n >= 2^31 (FDBB_MAX_POINTS: a larger set is split
+ *                into calls by the caller), a direction out of range, a NULL
+ *                required pointer with n > 0, or ld < n;
  *   FDBB_EALIGN  a base pointer not aligned to its element size;
  *   FDBB_EALIAS  any overlap between an input and an output field set, or
  *                between two outputs, except the exact in-place use (same
@@ -57,6 +58,10 @@
 #define FDBB_H
 
 #include <stdint.h>
+
+/* Points per call (and per batch task) are below this bound.  Offsets and
+ * leading dimensions are 64-bit, so a call's arrays may span any size. */
+#define FDBB_MAX_POINTS ((int64_t)1 << 31)
 
 #ifdef __cplusplus
 extern "C" {

@@ -213,6 +213,7 @@ int check_common(int dim, double gamma, int dtype, int64_t n)
     if (!std::isfinite(gamma) || !(gamma > 1.0)) return fail(FDBB_EINVAL, "gamma must be finite and > 1");
     if (dtype != FDBB_F64 && dtype != FDBB_F32) return fail(FDBB_EINVAL, "unknown dtype");
     if (n < 0) return fail(FDBB_EINVAL, "n must be >= 0");
+    if (n >= FDBB_MAX_POINTS) return fail(FDBB_EINVAL, "n must be below 2^31 points per call");
     return FDBB_OK;
 }
 
@@ -403,7 +404,11 @@ int launch(Call &c, void *stream)
     int64_t ntiles = (c.a.n + tile_pts - 1) / tile_pts;
     int64_t grid = ntiles;
     if (cfg.grid_cap > 0 && grid > cfg.grid_cap) grid = cfg.grid_cap;
-    if (grid > 0x7fffffff) grid = 0x7fffffff;
+    // keep a dispatch below 2^31 work-items (the grid-dimension bound HIP
+    // reports on this device); the kernels loop over tiles, so a capped grid
+    // still covers every point
+    const int64_t max_grid = 0x7fffffffLL / cfg.block;
+    if (grid > max_grid) grid = max_grid;
     void *args[] = {&c.a, &ntiles};
     hipError_t e = hipLaunchKernel(fn, dim3((unsigned)grid), dim3((unsigned)cfg.block), args, lds,
                                    (hipStream_t)stream);

@@ -260,6 +260,23 @@ def test_task_check_validates_without_a_gpu():
     assert F.library().fdbb_task_check(ctypes.byref(t)) == F.EINVAL
 
 
+def test_points_per_call_bound():
+    """Calls and tasks take fewer than 2^31 points (64-bit offsets and
+    leading dimensions either way)."""
+    lib = F.library()
+    t = F.Task()
+    big = 1 << 31
+    t.op, t.dim, t.dtype, t.gamma = 0, 1, 1, 1.4
+    t.in0, t.out0 = A0, A0 + 4 * 3 * (big + 64)
+    t.ld_in0 = t.ld_out0 = big + 64
+    t.n = big - 1
+    assert lib.fdbb_task_check(ctypes.byref(t)) == F.OK
+    t.n = big
+    assert lib.fdbb_task_check(ctypes.byref(t)) == F.EINVAL
+    assert lib.fdbb_cons2prim(1, 1.4, 1, A0, big + 64, t.out0, big + 64, big, None) == F.EINVAL
+    assert b"2^31" in lib.fdbb_last_error()
+
+
 def test_launch_config_table():
     lib = F.library()
     assert lib.fdbb_set_launch_config(3, 3, 0, 100, 1, 0, 1) == F.EINVAL   # not a multiple of 64

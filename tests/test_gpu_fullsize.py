@@ -171,3 +171,46 @@ def test_batched_512_blocks_sampled(dt, cfg):
     plan.close()
     del blocks
     torch.cuda.empty_cache()
+
+
+@pytest.mark.skip(reason="a run of this test (before calls were bounded to fewer than 2^31 points) ended "
+                  "in a GPU hardware exception whose cause was not found by reading the kernels or "
+                  "their assembly; such calls are now refused, and the case stays off the GPU")
+def test_1d_ops_beyond_2p31_points():
+    """Point indices and leading dimensions past 2^31 (64-bit indexing): the
+    1D ops of a step on 2^31 + 1000 points stored in FP32 (26 GB per field
+    set), sampled around the 2^31 boundary and the ragged tail against the
+    oracle."""
+    n = (1 << 31) + 1000
+    dt = "f32"
+    g = torch.Generator(device="cuda")
+    g.manual_seed(21)
+    V = F.empty_fields(3, n, torch.float32)
+    V[0].uniform_(0.5, 2.0, generator=g)
+    V[1].uniform_(-1.0, 1.0, generator=g)
+    V[2].uniform_(0.5, 2.0, generator=g)
+    U = F.empty_fields(3, n, torch.float32)
+    F.fdbb_prim2cons(1, GAMMA, V, U)
+    del V
+    rng = np.random.default_rng(22)
+    b = 1 << 31
+    idx = np.unique(np.concatenate([np.arange(2048), np.arange(b - 4096, b + 4096), np.arange(n - 2048, n),
+                                    rng.integers(0, n, 1 << 14)]))
+    it = torch.from_numpy(idx).cuda()
+    Uo = host(U[:, it]).astype(np.float64)
+    W = F.empty_fields(3, n, torch.float32)
+    F.fdbb_cons2prim(1, GAMMA, U, W)
+    assert group_error(host(W[:, it]), oracle.cons2prim(1, GAMMA, Uo), state_groups(1)) <= TOL[dt]
+    del W
+    p = torch.empty(n, dtype=torch.float32, device="cuda")
+    c = torch.empty(n, dtype=torch.float32, device="cuda")
+    F.fdbb_eos(1, GAMMA, U, p, c)
+    po, co = oracle.eos(1, GAMMA, Uo)
+    assert group_error(host(p[it])[None], po[None], [[0]]) <= TOL[dt]
+    assert group_error(host(c[it])[None], co[None], [[0]]) <= TOL[dt]
+    del p, c
+    Fo = F.empty_fields(3, n, torch.float32)
+    F.fdbb_flux(1, GAMMA, U, Fo)
+    assert group_error(host(Fo[:, it]), oracle.flux(1, GAMMA, Uo), flux_groups(1)) <= TOL[dt]
+    del Fo, U
+    torch.cuda.empty_cache()
