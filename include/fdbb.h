@@ -354,8 +354,8 @@ int fdbb_batch_exec(fdbb_batch_plan *plan, void *stream, int use_graph);
 /* The batch configuration that plans created with block == 0, the
  * allocation-free batch entry point with block == 0 and the request server
  * use, per storage type: block (64..256, multiple of 64), ppt (1, 2, 4, 8),
- * grid_per_cu workgroups per compute unit (0: 2048 / block), store mode
- * nontemporal (0, 1, 2 as for plans).  The binding installs the autotuned
+ * grid_per_cu workgroups per compute unit (0: 2048 / block; at most 1024),
+ * store mode nontemporal (0, 1, 2 as for plans).  The binding installs the autotuned
  * table's entry at load; until then 256 threads, 1 point per thread, the
  * default grid and streaming stores.  FDBB_EINVAL for values out of range
  * or a configuration whose 3D Jacobian staging would not fit in LDS. */

@@ -1203,7 +1203,7 @@ int fdbb_set_batch_config(int dtype, int block, int ppt, int grid_per_cu, int no
 {
     g_last_error.clear();
     if (dtype != FDBB_F64 && dtype != FDBB_F32) return fail(FDBB_EINVAL, "unknown dtype");
-    if (!batch_config_ok(block, ppt, nontemporal) || grid_per_cu < 0 || grid_per_cu > 64)
+    if (!batch_config_ok(block, ppt, nontemporal) || grid_per_cu < 0 || grid_per_cu > 1024)
         return fail(FDBB_EINVAL, "invalid batch configuration");
     // a plan of this configuration must be able to stage 3D Jacobian blocks
     if (lds_bytes(FDBB_OP_FLUX_JACOBIAN, 3, dtype, block, ppt) > 160 * 1024)
@@ -1219,7 +1219,7 @@ int fdbb_set_server_batch_config(int block, int ppt, int grid_per_cu, int nontem
         g_batch_cfg[2].store(0);
         return FDBB_OK;
     }
-    if (!batch_config_ok(block, ppt, nontemporal) || grid_per_cu < 0 || grid_per_cu > 64)
+    if (!batch_config_ok(block, ppt, nontemporal) || grid_per_cu < 0 || grid_per_cu > 1024)
         return fail(FDBB_EINVAL, "invalid batch configuration");
     if (lds_bytes(FDBB_OP_FLUX_JACOBIAN, 3, FDBB_F64, block, ppt) > 160 * 1024)
         return fail(FDBB_EINVAL, "batch configuration needs more LDS than a workgroup may use");

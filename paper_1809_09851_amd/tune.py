@@ -48,7 +48,7 @@ STORE_MODES = (1, 0)
 # compute unit x store mode (0 regular, 1 nt, 2 nt + sc1)
 BATCH_BLOCKS = (64, 128, 256)
 BATCH_PPTS = (1, 2, 4, 8)
-BATCH_GRID_PER_CU = (1, 2, 4, 8, 16)
+BATCH_GRID_PER_CU = (1, 2, 4, 8, 16, 64, 256, 1024)
 BATCH_STORE_MODES = (1, 2, 0)
 DEFAULT_TABLE = os.environ.get(
     "FDBB_TUNED_TABLE", os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_gfx950.json"))

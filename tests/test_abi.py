@@ -162,7 +162,7 @@ def test_server_batch_config():
         assert lib.fdbb_set_server_batch_config(256, 4, 0, 1) == F.EINVAL   # 3D FP64 staging beyond LDS
         assert lib.fdbb_set_server_batch_config(96, 1, 0, 1) == F.EINVAL
         assert lib.fdbb_set_server_batch_config(64, 3, 0, 1) == F.EINVAL
-        assert lib.fdbb_set_server_batch_config(64, 1, 65, 1) == F.EINVAL
+        assert lib.fdbb_set_server_batch_config(64, 1, 1025, 1) == F.EINVAL
         assert lib.fdbb_set_server_batch_config(64, 1, 0, 3) == F.EINVAL
         assert F.fdbb_get_server_batch_config() == (256, 1, 8, 1)
         F.fdbb_set_server_batch_config(0)
