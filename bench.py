@@ -92,6 +92,16 @@ def box_state(root: str = "/sys/class/drm"):
         vram = read(os.path.join(dev, "mem_info_vram_total"))
         if vram and vram.isdigit():
             out["vram_gib"] = round(int(vram) / 2 ** 30, 1)
+        used = read(os.path.join(dev, "mem_info_vram_used"))
+        if used and used.isdigit():
+            out["vram_used_at_start_gib"] = round(int(used) / 2 ** 30, 3)
+        # pages the driver has retired for memory errors (one line each)
+        bad = read(os.path.join(dev, "ras", "gpu_vram_bad_pages"))
+        if bad is not None:
+            out["retired_vram_pages"] = sum(1 for ln in bad.splitlines() if ln.strip())
+        fclk = current_level(read(os.path.join(dev, "pp_dpm_fclk")))
+        if fclk:
+            out["fabric_clock"] = fclk
         return out
     return None
 

@@ -67,6 +67,10 @@ def test_box_state_reads_the_driver_files(tmp_path):
     (dev / "pp_dpm_sclk").write_text("0: 500Mhz \n1: 158Mhz *\n2: 2400Mhz \n")
     (dev / "hwmon" / "hwmon3" / "power1_cap").write_text("1400000000\n")
     (dev / "mem_info_vram_total").write_text(str(288 * 2 ** 30) + "\n")
+    (dev / "mem_info_vram_used").write_text(str(3 * 2 ** 29) + "\n")
+    (dev / "ras").mkdir()
+    (dev / "ras" / "gpu_vram_bad_pages").write_text("0x1 : 0x1000 : R\n0x2 : 0x1000 : R\n")
+    (dev / "pp_dpm_fclk").write_text("0: 1200Mhz *\n1: 2000Mhz \n")
     other = tmp_path / "card1" / "device"
     other.mkdir(parents=True)
     (other / "vendor").write_text("0x8086\n")
@@ -75,4 +79,6 @@ def test_box_state_reads_the_driver_files(tmp_path):
     assert s["hbm_clock"] == "2000Mhz"
     assert s["gfx_clock_levels"] == ["500Mhz", "158Mhz", "2400Mhz"]
     assert s["power_cap_w"] == 1400.0 and s["vram_gib"] == 288.0
+    assert s["vram_used_at_start_gib"] == 1.5 and s["retired_vram_pages"] == 2
+    assert s["fabric_clock"] == "1200Mhz"
     assert bench.box_state(str(tmp_path / "none")) is None
