@@ -219,3 +219,23 @@ def test_per_direction_flux_requests(pools):
         assert time.time() < t_end
     assert srv.stats()["arena_bytes"] == 0
     srv.close()
+
+
+@pytest.mark.parametrize("cfg", [(64, 1, 2, 0), (256, 2, 4, 2), (128, 4, 1024, 1)])
+def test_server_batch_configurations(pools, cfg):
+    """Servers created under other batch configurations (small and large
+    workgroups, few and many per CU, each store mode) give oracle results;
+    the configuration is read when a server is created."""
+    saved = F.fdbb_get_server_batch_config()
+    F.fdbb_set_server_batch_config(*cfg)
+    try:
+        srv = S.NativeServer(8 * 10 ** 9, slots=2, max_batch=16, max_batch_bytes=1e12, mode="batched")
+    finally:
+        F.fdbb_set_server_batch_config(*saved)
+    reqs = _requests(pools, 24, 40 + cfg[0] + cfg[1])
+    out = _run(srv, reqs)
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == 24 and st["launches"] < 24
+    for k, r in enumerate(reqs):
+        _check(r, out[k])
