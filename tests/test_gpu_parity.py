@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 DIMS = (1, 2, 3)
 DTS = ("f64", "f32")
-SIZES = (1, 63, 64, 65, 1000, 5003)
+SIZES = (1, 63, 64, 65, 1000, 5003, 12305)
 
 
 @pytest.fixture(scope="module", autouse=True)
