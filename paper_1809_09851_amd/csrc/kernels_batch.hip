@@ -1,8 +1,11 @@
-// Persistent batch kernel: a fixed grid of workgroups walks the tiles of
-// many independent tasks of uneven size.  Tiles are dealt round-robin
-// (tile t to workgroup t mod gridDim.x); the owning task of a tile is found
-// by binary search in the tile prefix sums.  Every tile costs about the
-// same, so the static deal balances without a shared counter.
+// Batch kernel: a grid of workgroups walks the tiles of many independent
+// tasks of uneven size.  Tiles are dealt round-robin (tile t to workgroup
+// t mod gridDim.x); the owning task of a tile is found by binary search in
+// the tile prefix sums.  Every tile costs about the same, so the static
+// deal balances without a shared counter.  The grid is part of the launch
+// configuration: a few workgroups per compute unit make the launch
+// persistent, a grid near the tile count leaves the order of tiles to the
+// hardware dispatcher (the tuned FP32 shape).
 #include "fdbb_internal.hpp"
 
 #include <atomic>
