@@ -239,3 +239,25 @@ def test_server_batch_configurations(pools, cfg):
     assert st["completed"] == 24 and st["launches"] < 24
     for k, r in enumerate(reqs):
         _check(r, out[k])
+
+
+@pytest.mark.parametrize("mode", ["batched", "single"])
+def test_empty_and_one_point_requests(pools, mode):
+    """Requests of 0 and 1 point complete (alone and among others) and the
+    one-point results match the oracle."""
+    reqs = _requests(pools, 6, 41)
+    for k, r in enumerate(reqs):
+        r.n = 0 if k % 2 == 0 else 1
+        r.U = r.U[:, :r.n]
+        if r.Fbar is not None:
+            r.Fbar = r.Fbar[:, :r.n]
+    srv = S.NativeServer(8 * 10 ** 9, slots=2, max_batch=8, max_batch_bytes=1e12, mode=mode)
+    out = _run(srv, reqs)
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == 6 and st["arena_bytes"] == 0
+    for k, r in enumerate(reqs):
+        if r.n == 1:
+            _check(r, out[k])
+        else:
+            assert out[k].shape[-1] == 0 or out[k].shape[1] == 0
