@@ -286,3 +286,36 @@ def test_direct_launches_size_lds_to_the_task_list():
                 else:
                     assert group_error(host(out), oracle.flux(dim, GAMMA, Uo), flux_groups(dim)) <= TOL[dt]
     plan.close()
+
+
+def test_plans_with_empty_and_one_point_tasks():
+    """Tasks of 0 and 1 point among others: the empty ones leave their
+    outputs untouched, the rest match the oracle; an all-empty list runs
+    nothing."""
+    tasks, checks, alive = [], [], []
+    for k, n in enumerate((0, 1, 0, 777, 1, 0, 4099)):
+        Uo, Ug = states(3, max(n, 1), 700 + k, "f64")
+        Ug = Ug[:, :n]
+        Uo = Uo[:, :n]
+        Fo = F.empty_fields(15, max(n, 1))[:, :n]
+        tasks.append(B.flux_task(Ug, Fo, GAMMA))
+        checks.append((Uo, Fo))
+        alive.append(Ug)
+    sentinel = F.empty_fields(15, 64).fill_(7.0)
+    empty_task = B.flux_task(F.empty_fields(5, 64)[:, :0], sentinel[:, :0], GAMMA)
+    plan = B.Plan(tasks + [empty_task], capacity=16)
+    assert plan.info()[0] == 1 + 777 + 1 + 4099
+    for graph in (False, True):
+        plan.run(graph=graph)
+        torch.cuda.synchronize()
+        for Uo, Fo in checks:
+            if Uo.shape[1]:
+                assert group_error(host(Fo), oracle.flux(3, GAMMA, Uo), flux_groups(3)) <= TOL["f64"]
+        assert bool((sentinel == 7.0).all())
+    plan.update([empty_task])
+    assert plan.info() == (0, 0)
+    plan.run(graph=False)
+    plan.run(graph=True)
+    torch.cuda.synchronize()
+    assert bool((sentinel == 7.0).all())
+    plan.close()
