@@ -150,3 +150,38 @@ def test_1d_ops_on_both_sides_of_the_small_bound(op):
             assert group_error(host(c)[None], co[None], [[0]]) <= TOL["f64"]
         else:
             assert group_error(host(F.flux(Ug, GAMMA)), oracle.flux(1, GAMMA, Uo), flux_groups(1)) <= TOL["f64"]
+
+
+@pytest.fixture
+def large_configs_only():
+    """Lift every small-launch entry for the test, so that calls of any size
+    run with the large (2 GB-tuned) configurations; restored afterwards."""
+    saved = []
+    for op in F.OPS:
+        for dim in (1, 2, 3):
+            for code in (F.F64, F.F32):
+                entry = F.fdbb_get_small_launch_config(op, dim, code)
+                if entry[0]:
+                    saved.append((op, dim, code, entry))
+                    F.fdbb_set_small_launch_config(op, dim, code, 0)
+    yield
+    for op, dim, code, entry in saved:
+        F.fdbb_set_small_launch_config(op, dim, code, *entry)
+
+
+@pytest.mark.parametrize("dt", ("f64", "f32"))
+@pytest.mark.parametrize("dim", (1, 2, 3))
+def test_every_op_with_its_installed_large_configuration(large_configs_only, dim, dt):
+    """The parity checks of every entry point, on a ragged multi-tile size,
+    with the configurations calls above the small-launch bound use."""
+    import test_gpu_parity as P
+    n = 5003
+    assert F.fdbb_launch_config_for("cons2char", dim, F.F64 if dt == "f64" else F.F32, n) == \
+        F.fdbb_get_launch_config("cons2char", dim, F.F64 if dt == "f64" else F.F32)
+    for fn in (P.test_cons2prim, P.test_prim2cons, P.test_eos, P.test_velocity_magnitude2, P.test_flux,
+               P.test_flux_jacobian, P.test_riemann_invariants, P.test_characteristic_transforms,
+               P.test_flux_direction, P.test_fused, P.test_adjoint, P.test_eigenvectors, P.test_char_apply,
+               P.test_roe_average, P.test_viscous_flux):
+        fn(dim, dt, n)
+    for case in range(len(P.EOS_CASES)):
+        P.test_eos_pvt(dim, dt, n, case)
