@@ -1,7 +1,8 @@
 // Batch kernel: a grid of workgroups walks the tiles of many independent
 // tasks of uneven size.  Tiles are dealt round-robin (tile t to workgroup
-// t mod gridDim.x); the owning task of a tile is found by binary search in
-// the tile prefix sums.  Every tile costs about the same, so the static
+// t mod gridDim.x); the owning task of a tile is found in the tile prefix
+// sums by a galloping search from the workgroup's previous task (tiles
+// only move forward).  Every tile costs about the same, so the static
 // deal balances without a shared counter.  The grid is part of the launch
 // configuration: a few workgroups per compute unit make the launch
 // persistent, a grid near the tile count leaves the order of tiles to the
@@ -42,8 +43,17 @@ __global__ __launch_bounds__(kMaxBlockStaged) void k_batch(const TaskDev *__rest
     const int ntasks = (int)header[0];
     const int64_t ntiles = header[1];
     const int64_t tile_pts = (int64_t)blockDim.x * P;
+    int lo = 0;  // owning task of the previous tile: tiles only move forward
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        int lo = 0, hi = ntasks - 1;
+        // last task whose first tile is <= t: gallop forward from the
+        // previous owner, then bisect the bracket (one load when the tile
+        // stays in the same task)
+        int step = 1;
+        while (lo + step < ntasks && prefix[lo + step] <= t) {
+            lo += step;
+            step <<= 1;
+        }
+        int hi = (lo + step < ntasks ? lo + step : ntasks) - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (prefix[mid] <= t) lo = mid;
